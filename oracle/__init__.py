@@ -1,0 +1,229 @@
+"""FP64 CPU oracle for the Gaussian-mixture checkpoint-restart hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the library and its Python
+binding never do.  The arithmetic lives in ``gm_oracle.c`` (plain loops,
+FP64, written from the paper); this module only marshals numpy arrays.
+
+Parity status (see each test module): compress, finish, reconstruct and
+Philox are pinned (closed forms, library special cases, invariants,
+known-answer values); the choice among local maxima on general data is
+"parity unpinned" beyond the shared initialisation rule.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libgmoracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("gm_oracle.c", "gm_oracle_mlp.c") if os.path.exists(os.path.join(_HERE, f))]
+
+STATUS = {
+    "SMALL_CELL_K1": 1 << 0, "K0_CAPPED": 1 << 1, "COV_FLOOR": 1 << 2, "MAXSWEEPS": 1 << 3,
+    "NEAR_TIE": 1 << 4, "WARM_FALLBACK": 1 << 5, "NONFINITE_INPUT": 1 << 6,
+    "LEMONS_SKIPPED": 1 << 7, "DEGENERATE": 1 << 8,
+}
+MODE_STANDARD_EM = 1
+MODE_NO_FINISH = 2
+
+
+def build(force=False):
+    """Compile the oracle with gcc (-O2, plain C, pthreads)."""
+    if not force and os.path.exists(_SO) and all(os.path.getmtime(_SO) >= os.path.getmtime(s) for s in _SRC):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+           "-o", tmp] + _SRC + ["-lm", "-lpthread"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_SO)
+        _declare(_lib)
+    return _lib
+
+
+P = ctypes.c_void_p
+I32, I64, F64, U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+
+
+def _declare(L):
+    L.orc_philox4x64_10.argtypes = [P, P, P]
+    L.orc_philox4x64_10.restype = None
+    L.orc_compress.argtypes = [P, P, P, I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, F64, U64,
+                               ctypes.c_int, F64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+    L.orc_compress.restype = ctypes.c_int
+    L.orc_init_indices.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P]
+    L.orc_init_indices.restype = None
+    L.orc_mle_finish.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P]
+    L.orc_mle_finish.restype = ctypes.c_int
+    L.orc_penalised_L.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, F64]
+    L.orc_penalised_L.restype = F64
+    L.orc_reconstruct.argtypes = [P, P, P, P, ctypes.c_int, P, P, I64, ctypes.c_int, ctypes.c_int, U64,
+                                  P, P, P, P, P, ctypes.c_int]
+    L.orc_reconstruct.restype = ctypes.c_int
+    if hasattr(L, "orc_features"):
+        _declare_mlp(L)
+
+
+def _declare_mlp(L):
+    L.orc_features.argtypes = [P, P, P, I64, P, ctypes.c_int]
+    L.orc_features.restype = ctypes.c_int
+    L.orc_mlp_forward.argtypes = [P, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+    L.orc_mlp_forward.restype = ctypes.c_int
+    L.orc_mlp_loss_backward.argtypes = [P, ctypes.c_int, P, P, P, P, P, P, P, F64, ctypes.c_int,
+                                        P, P, P, P, P, P, P]
+    L.orc_mlp_loss_backward.restype = F64
+    L.orc_warm_decode.argtypes = [P, P, P, I64, ctypes.c_int, P, P, P, P]
+    L.orc_warm_decode.restype = ctypes.c_int
+    L.orc_warm_targets.argtypes = [P, P, P, P, P, I64, ctypes.c_int, P]
+    L.orc_warm_targets.restype = ctypes.c_int
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def default_threads():
+    n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def ntri(D):
+    return D * (D + 1) // 2
+
+
+def philox4x64_10(ctr, key):
+    c = _c(ctr, np.uint64)
+    k = _c(key, np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def init_indices(n, K0, seed, cell):
+    perm = np.zeros(n, dtype=np.int32)
+    lib().orc_init_indices(n, K0, seed, cell, _p(perm))
+    return perm[:K0].copy()
+
+
+def compress(v, alpha, cell_off, kmax, seed, D=None, n_min=10, max_sweeps=1000, fixed_sweeps=None, tol=1e-7,
+             mode=0, T=-1.0, init=None, trace=False, nthreads=None):
+    """Adaptive EM-GM compress of every cell (FP64).  Returns a dict of arrays.
+
+    ``init`` (optional): dict with K [n_cells], omega [n_cells, kmax],
+    mu [n_cells, kmax, D] (original coordinates), sigma [n_cells, kmax, ntri(D)];
+    cells with K > 0 start from it instead of the random cold start.
+    """
+    v = _c(v, np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    D = v.shape[1] if D is None else D
+    alpha = _c(alpha, np.float64)
+    off = _c(cell_off, np.int64)
+    n_cells = len(off) - 1
+    nt = ntri(D)
+    out = {
+        "K": np.zeros(n_cells, np.int32), "omega": np.zeros((n_cells, kmax)),
+        "mu": np.zeros((n_cells, kmax, D)), "sigma": np.zeros((n_cells, kmax, nt)),
+        "moments": np.zeros((n_cells, 1 + D + nt)), "L_pen": np.zeros(n_cells), "L_final": np.zeros(n_cells),
+        "sweeps": np.zeros(n_cells, np.int32), "status": np.zeros(n_cells, np.int32),
+        "visits": np.zeros(n_cells, np.int64),
+    }
+    fs = None if fixed_sweeps is None else _c(np.broadcast_to(fixed_sweeps, (n_cells,)), np.int32)
+    Lt = Kt = None
+    if trace:
+        Lt = np.full((n_cells, max_sweeps), np.nan)
+        Kt = np.zeros((n_cells, max_sweeps), np.int32)
+    iK = iw = imu = iS = None
+    if init is not None:
+        iK = _c(init["K"], np.int32)
+        iw = _c(init["omega"], np.float64)
+        imu = _c(init["mu"], np.float64)
+        iS = _c(init["sigma"], np.float64)
+    rc = lib().orc_compress(_p(v), _p(alpha), _p(off), n_cells, D, kmax, n_min, max_sweeps, _p(fs), tol, seed, mode,
+                            float(T), _p(iK), _p(iw), _p(imu), _p(iS), _p(out["K"]), _p(out["omega"]),
+                            _p(out["mu"]), _p(out["sigma"]), _p(out["moments"]), _p(out["L_pen"]),
+                            _p(out["L_final"]), _p(out["sweeps"]), _p(out["status"]), _p(out["visits"]), _p(Lt),
+                            _p(Kt), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("orc_compress rejected its arguments")
+    if trace:
+        out["L_trace"] = Lt
+        out["K_trace"] = Kt
+    return out
+
+
+def mle_finish(v, alpha, omega, mu, sigma):
+    """One unpenalised joint EM step on one cell from an arbitrary mixture."""
+    v = _c(v, np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    n, D = v.shape
+    w = _c(omega, np.float64).copy()
+    m = _c(mu, np.float64).copy()
+    S = _c(sigma, np.float64).copy()
+    rc = lib().orc_mle_finish(_p(v), _p(_c(alpha, np.float64)), n, D, len(w), _p(w), _p(m), _p(S))
+    if rc != 0:
+        raise ValueError("mle_finish: a covariance is not positive definite")
+    return w, m, S
+
+
+def penalised_L(v, alpha, omega, mu, sigma, T=-1.0):
+    v = _c(v, np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    n, D = v.shape
+    return lib().orc_penalised_L(_p(v), _p(_c(alpha, np.float64)), n, D, len(omega), _p(_c(omega, np.float64)),
+                                 _p(_c(mu, np.float64)), _p(_c(sigma, np.float64)), float(T))
+
+
+def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stats=False, nthreads=None):
+    K = _c(K, np.int32)
+    omega = _c(omega, np.float64)
+    kmax = omega.shape[1]
+    mu = _c(mu, np.float64)
+    sigma = _c(sigma, np.float64)
+    off = _c(out_off, np.int64)
+    target = _c(target, np.float64)
+    n_cells = len(off) - 1
+    n = int(off[-1])
+    v = np.zeros((n, D))
+    w = np.zeros(n)
+    x = np.zeros((n, dx)) if dx > 0 else None
+    st = np.zeros(n_cells, np.int32)
+    sb = np.zeros((n_cells, 4)) if stats else None
+    rc = lib().orc_reconstruct(_p(K), _p(omega), _p(mu), _p(sigma), kmax, _p(off), _p(target), n_cells, D, dx, seed,
+                               _p(v), _p(w), _p(x), _p(st), _p(sb), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("orc_reconstruct rejected its arguments")
+    out = {"v": v, "w": w, "x": x, "status": st}
+    if stats:
+        out["stats"] = sb
+    return out
+
+
+def targets_from_moments(moments, D):
+    """Reconstruction targets (W, P, E = tr(S)/2) from the compress moments record."""
+    mom = np.asarray(moments)
+    W = mom[:, 0]
+    P = mom[:, 1:1 + D]
+    diag = [1 + D + i * D - i * (i - 1) // 2 for i in range(D)]
+    E = 0.5 * sum(mom[:, j] for j in diag)
+    return np.concatenate([W[:, None], P, E[:, None]], axis=1)

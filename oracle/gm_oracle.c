@@ -1,0 +1,894 @@
+/*
+ * gm_oracle.c -- plain, slow FP64 CPU oracle for the Gaussian-mixture
+ * checkpoint-restart method of Chen, Chacon & Nguyen, "Gaussian-mixture
+ * checkpoint-restart for particle-in-cell" (arXiv:2007.12273).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP library: every formula below is written again from
+ * the paper.
+ *
+ * Every loop is written in the order the paper states it: no blocking, no
+ * fusion, no incremental denominators.  The component-wise E-step recomputes
+ * all log-densities of all particles for every component update, which makes
+ * one sweep O(n K^2).  That is deliberate.
+ *
+ * Threads split the cell range into contiguous chunks; each cell is computed
+ * by exactly one thread, so results do not depend on the thread count.
+ *
+ * Parity status of each function is listed at its definition.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXK 32
+#define ORC_MAXD 3
+
+/* per-cell status bits (the library documents the same values) */
+#define ORC_SMALL_CELL_K1 (1 << 0)
+#define ORC_K0_CAPPED (1 << 1)
+#define ORC_COV_FLOOR (1 << 2)
+#define ORC_MAXSWEEPS (1 << 3)
+#define ORC_NEAR_TIE (1 << 4)
+#define ORC_WARM_FALLBACK (1 << 5)
+#define ORC_NONFINITE_INPUT (1 << 6)
+#define ORC_LEMONS_SKIPPED (1 << 7)
+#define ORC_DEGENERATE (1 << 8)
+
+/* oracle mode flags */
+#define ORC_MODE_STANDARD_EM 1 /* joint E-step, MLE weights, no annihilation */
+#define ORC_MODE_NO_FINISH 2   /* report the penalised state, skip the unpenalised step */
+
+static const double LN_2PI = 1.8378770664093454835606594728112;
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 counter-based generator (Salmon, Moraes, Dror & Shaw, */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11).             */
+/* Pinned against numpy.random.Philox in the tests.                   */
+/* ------------------------------------------------------------------ */
+static void mul128(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo)
+{
+    __uint128_t p = (__uint128_t)a * (__uint128_t)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128(M0, c[0], &hi0, &lo0);
+        mul128(M1, c[2], &hi1, &lo1);
+        uint64_t n0 = hi1 ^ c[1] ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c[3] ^ k1;
+        uint64_t n3 = lo0;
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+    }
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
+}
+
+/* 53 random bits -> double in [0, 1) */
+static double u53(uint64_t x) { return (double)(x >> 11) * (1.0 / 9007199254740992.0); }
+
+#define ORC_TAG_INIT 0x494E4954ULL  /* "INIT" */
+#define ORC_TAG_RECON 0x5245434FULL /* "RECO" */
+
+/* ------------------------------------------------------------------ */
+/* small dense linear algebra (D <= 3), row-major D x D                */
+/* ------------------------------------------------------------------ */
+
+/* Cholesky S = L L^T; returns 0 on success, -1 if S is not positive definite. */
+static int chol(int D, const double S[ORC_MAXD][ORC_MAXD], double L[ORC_MAXD][ORC_MAXD])
+{
+    for (int i = 0; i < ORC_MAXD; ++i)
+        for (int j = 0; j < ORC_MAXD; ++j) L[i][j] = 0.0;
+    for (int j = 0; j < D; ++j) {
+        double s = S[j][j];
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0) || !isfinite(s)) return -1;
+        L[j][j] = sqrt(s);
+        for (int i = j + 1; i < D; ++i) {
+            double t = S[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    return 0;
+}
+
+/* ln N(x; mu, Sigma) with Sigma = L L^T:
+ *   -D/2 ln 2pi - 1/2 ln|Sigma| - 1/2 (x-mu)^T Sigma^-1 (x-mu)   (Sec. 2, Gaussian density)
+ * The quadratic form is |y|^2 with L y = x - mu (forward substitution). */
+static double log_normal(int D, const double* x, const double* mu, const double L[ORC_MAXD][ORC_MAXD])
+{
+    double y[ORC_MAXD];
+    double logdet = 0.0, q = 0.0;
+    for (int i = 0; i < D; ++i) {
+        double t = x[i] - mu[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+        q += y[i] * y[i];
+        logdet += 2.0 * log(L[i][i]);
+    }
+    return -0.5 * D * LN_2PI - 0.5 * logdet - 0.5 * q;
+}
+
+/* ------------------------------------------------------------------ */
+/* mixture state of one cell                                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int K;
+    double w[ORC_MAXK];
+    double mu[ORC_MAXK][ORC_MAXD];
+    double S[ORC_MAXK][ORC_MAXD][ORC_MAXD];
+    double L[ORC_MAXK][ORC_MAXD][ORC_MAXD];
+} mixture;
+
+static void remove_component(mixture* m, int k)
+{
+    for (int j = k; j + 1 < m->K; ++j) {
+        m->w[j] = m->w[j + 1];
+        memcpy(m->mu[j], m->mu[j + 1], sizeof(m->mu[j]));
+        memcpy(m->S[j], m->S[j + 1], sizeof(m->S[j]));
+        memcpy(m->L[j], m->L[j + 1], sizeof(m->L[j]));
+    }
+    m->K -= 1;
+}
+
+/* renormalise the mixing weights to sum 1 (Sec. 2.3, step 3) */
+static void renormalise(mixture* m)
+{
+    double s = 0.0;
+    for (int j = 0; j < m->K; ++j) s += m->w[j];
+    for (int j = 0; j < m->K; ++j) m->w[j] /= s;
+}
+
+/* ln sum_j w_j f_j(x) by log-sum-exp; also returns ell_j = ln w_j + ln f_j(x) */
+static double mixture_lse(int D, const mixture* m, const double* x, double* ell)
+{
+    double mx = -INFINITY;
+    for (int j = 0; j < m->K; ++j) {
+        ell[j] = log(m->w[j]) + log_normal(D, x, m->mu[j], m->L[j]);
+        if (ell[j] > mx) mx = ell[j];
+    }
+    double s = 0.0;
+    for (int j = 0; j < m->K; ++j) s += exp(ell[j] - mx);
+    return mx + log(s);
+}
+
+/* Penalised log-likelihood, eq. (lnL-GM):
+ *   L = sum_p a_p ln sum_k w_k f_k(v_p) - d/2 ln N - T/2 sum_k ln w_k,
+ * with T = D(D+3)/2 parameters per component and d = K T + K - 1 in total
+ * (Appendix A).  N = sum_p a_p. */
+static double penalised_L(int D, double T, const mixture* m, int n, const double* x, const double* a, double N)
+{
+    double ell[ORC_MAXK];
+    double ll = 0.0;
+    for (int p = 0; p < n; ++p) ll += a[p] * mixture_lse(D, m, x + (size_t)p * D, ell);
+    double d = m->K * T + m->K - 1;
+    double pen = 0.0;
+    for (int k = 0; k < m->K; ++k) pen += log(m->w[k]);
+    return ll - 0.5 * d * log(N) - 0.5 * T * pen;
+}
+
+/* Cholesky of component k with the covariance floor used when it fails
+ * (the paper is silent on singular covariances): add eps*I, eps = 1e-12 tr(C)/D,
+ * growing tenfold until it factors.  Returns 1 if a floor was added. */
+static int factor_component(int D, mixture* m, int k, double trC)
+{
+    if (chol(D, (const double(*)[ORC_MAXD])m->S[k], m->L[k]) == 0) return 0;
+    double eps = 1e-12 * trC / D;
+    for (int it = 0; it < 40; ++it) {
+        for (int i = 0; i < D; ++i) m->S[k][i][i] += eps;
+        if (chol(D, (const double(*)[ORC_MAXD])m->S[k], m->L[k]) == 0) return 1;
+        eps *= 10.0;
+    }
+    return 1;
+}
+
+/* Cold-start particle choice: partial Fisher-Yates over 0..n-1.  Draw j uses
+ * Philox with key (seed, "INIT") and counter (j, cell, 0, 0); the swap target
+ * is j + floor(x (n - j) / 2^64) for the first 64-bit output x.  On return
+ * perm[0..K0-1] are the chosen indices (perm must hold n ints). */
+void orc_init_indices(int n, int K0, uint64_t seed, uint64_t cell, int* perm)
+{
+    for (int p = 0; p < n; ++p) perm[p] = p;
+    uint64_t key[2] = {seed, ORC_TAG_INIT};
+    for (int j = 0; j < K0; ++j) {
+        uint64_t ctr[4] = {(uint64_t)j, cell, 0, 0}, r4[4];
+        orc_philox4x64_10(ctr, key, r4);
+        uint64_t hi, lo;
+        mul128(r4[0], (uint64_t)(n - j), &hi, &lo);
+        int r = j + (int)hi;
+        int t = perm[j];
+        perm[j] = perm[r];
+        perm[r] = t;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* compress                                                            */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    /* inputs */
+    const double* v;
+    const double* alpha;
+    const int64_t* off;
+    int64_t n_cells;
+    int D, kmax, n_min, max_sweeps;
+    const int32_t* fixed_sweeps; /* nullable; >0 = run exactly that many */
+    double tol;
+    uint64_t seed;
+    int mode;
+    double T_override; /* < 0: use D(D+3)/2 */
+    /* optional initial mixtures (warm start / test init), nullable */
+    const int32_t* init_K;
+    const double* init_w;
+    const double* init_mu;
+    const double* init_S; /* packed upper triangle */
+    /* outputs, padded to kmax */
+    int32_t* K;
+    double* w;
+    double* mu;
+    double* S;      /* packed upper triangle, D(D+1)/2 per component */
+    double* mom;    /* W, P[D], S[D(D+1)/2] */
+    double* L_pen;
+    double* L_final;
+    int32_t* sweeps;
+    int32_t* status;
+    int64_t* visits;   /* component E/M updates performed */
+    double* L_trace;   /* nullable: [n_cells * max_sweeps] penalised L after each sweep */
+    int32_t* K_trace;  /* nullable: [n_cells * max_sweeps] live K after each sweep */
+} compress_job;
+
+static int ntri(int D) { return D * (D + 1) / 2; }
+
+static void pack_sym(int D, const double S[ORC_MAXD][ORC_MAXD], double* out)
+{
+    int t = 0;
+    for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j) out[t++] = S[i][j];
+}
+
+static void unpack_sym(int D, const double* in, double S[ORC_MAXD][ORC_MAXD])
+{
+    int t = 0;
+    for (int i = 0; i < D; ++i)
+        for (int j = i; j < D; ++j) {
+            S[i][j] = in[t];
+            S[j][i] = in[t];
+            ++t;
+        }
+}
+
+/* One E-step for component k (eq. responsibility):
+ *   gamma_pk = a_p w_k f_k(v_p) / sum_j w_j f_j(v_p)
+ * using the current parameters of all live components. */
+static void responsibilities(int D, const mixture* m, int k, int n, const double* x, const double* a, double* g)
+{
+    double ell[ORC_MAXK];
+    for (int p = 0; p < n; ++p) {
+        double lse = mixture_lse(D, m, x + (size_t)p * D, ell);
+        g[p] = a[p] * exp(ell[k] - lse);
+    }
+}
+
+/* M-step for one component from its responsibilities, eqs. (muk), (sigmak):
+ *   mu_k = sum_p g_p v_p / N_k;  Sigma_k = sum_p g_p (v_p - mu_k)(v_p - mu_k)^T / N_k
+ * (the covariance uses the new mean). */
+static void mean_cov(int D, int n, const double* x, const double* g, double Nk, double* mu, double S[ORC_MAXD][ORC_MAXD])
+{
+    for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+        for (int p = 0; p < n; ++p) s += g[p] * x[(size_t)p * D + i];
+        mu[i] = s / Nk;
+    }
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+            for (int p = 0; p < n; ++p) s += g[p] * (x[(size_t)p * D + i] - mu[i]) * (x[(size_t)p * D + j] - mu[j]);
+            S[i][j] = s / Nk;
+        }
+}
+
+/* Unpenalised ("MLE") finish, Sec. 2.3.1: one joint E-step with the final
+ * parameters, then eqs. (muk), (sigmak) and w_k = N_k / N (eq. omegak-mle).
+ * Returns 0, or -1 if a resulting covariance is not positive definite. */
+static int mle_finish(int D, mixture* m, int n, const double* x, const double* a, double N, double* g_all)
+{
+    double ell[ORC_MAXK];
+    int K = m->K;
+    /* joint E-step: every gamma_p. comes from the same parameters */
+    for (int p = 0; p < n; ++p) {
+        double lse = mixture_lse(D, m, x + (size_t)p * D, ell);
+        for (int k = 0; k < K; ++k) g_all[(size_t)k * n + p] = a[p] * exp(ell[k] - lse);
+    }
+    mixture out = *m;
+    for (int k = 0; k < K; ++k) {
+        const double* g = g_all + (size_t)k * n;
+        double Nk = 0.0;
+        for (int p = 0; p < n; ++p) Nk += g[p];
+        mean_cov(D, n, x, g, Nk, out.mu[k], out.S[k]);
+        out.w[k] = Nk / N;
+        if (chol(D, (const double(*)[ORC_MAXD])out.S[k], out.L[k]) != 0) return -1;
+    }
+    *m = out;
+    return 0;
+}
+
+static void write_mixture(const compress_job* J, int64_t c, const mixture* m, const double* mean)
+{
+    int D = J->D, kmax = J->kmax, nt = ntri(D);
+    J->K[c] = m->K;
+    for (int k = 0; k < kmax; ++k) {
+        double* wo = J->w + (size_t)c * kmax + k;
+        double* mo = J->mu + ((size_t)c * kmax + k) * D;
+        double* so = J->S + ((size_t)c * kmax + k) * nt;
+        if (k < m->K) {
+            *wo = m->w[k];
+            for (int i = 0; i < D; ++i) mo[i] = m->mu[k][i] + mean[i];
+            pack_sym(D, (const double(*)[ORC_MAXD])m->S[k], so);
+        } else {
+            *wo = 0.0;
+            for (int i = 0; i < D; ++i) mo[i] = 0.0;
+            for (int i = 0; i < nt; ++i) so[i] = 0.0;
+        }
+    }
+}
+
+static void compress_cell(const compress_job* J, int64_t c, double* x, double* a, double* g)
+{
+    const int D = J->D, nt = ntri(D);
+    const int64_t o0 = J->off[c], o1 = J->off[c + 1];
+    const int n = (int)(o1 - o0);
+    const double T = J->T_override >= 0.0 ? J->T_override : 0.5 * D * (D + 3);
+    const double* v = J->v + (size_t)o0 * D;
+    const double* al = J->alpha + o0;
+    int32_t status = 0;
+    mixture m;
+    memset(&m, 0, sizeof(m));
+    double* mom = J->mom + (size_t)c * (1 + D + nt);
+    for (int i = 0; i < 1 + D + nt; ++i) mom[i] = 0.0;
+    J->L_pen[c] = 0.0;
+    J->L_final[c] = 0.0;
+    J->sweeps[c] = 0;
+    J->visits[c] = 0;
+
+    /* invalid input: non-finite values or non-positive weights */
+    for (int p = 0; p < n; ++p) {
+        int bad = !isfinite(al[p]) || !(al[p] > 0.0);
+        for (int i = 0; i < D; ++i) bad |= !isfinite(v[(size_t)p * D + i]);
+        if (bad) {
+            double zero[ORC_MAXD] = {0, 0, 0};
+            m.K = 0;
+            write_mixture(J, c, &m, zero);
+            J->status[c] = ORC_NONFINITE_INPUT;
+            return;
+        }
+    }
+    if (n == 0) {
+        double zero[ORC_MAXD] = {0, 0, 0};
+        m.K = 0;
+        write_mixture(J, c, &m, zero);
+        J->status[c] = ORC_DEGENERATE;
+        return;
+    }
+
+    /* O1: preserved moments W = sum a, P = sum a v, S = sum a v v^T (Sec. 2.4.2),
+     * mean m = P / W and the weighted covariance about it (two passes). */
+    double W = 0.0, P[ORC_MAXD] = {0, 0, 0}, S2[ORC_MAXD][ORC_MAXD];
+    memset(S2, 0, sizeof(S2));
+    for (int p = 0; p < n; ++p) {
+        W += al[p];
+        for (int i = 0; i < D; ++i) {
+            P[i] += al[p] * v[(size_t)p * D + i];
+            for (int j = 0; j < D; ++j) S2[i][j] += al[p] * v[(size_t)p * D + i] * v[(size_t)p * D + j];
+        }
+    }
+    mom[0] = W;
+    for (int i = 0; i < D; ++i) mom[1 + i] = P[i];
+    pack_sym(D, (const double(*)[ORC_MAXD])S2, mom + 1 + D);
+    double mean[ORC_MAXD] = {0, 0, 0};
+    for (int i = 0; i < D; ++i) mean[i] = P[i] / W;
+    double C[ORC_MAXD][ORC_MAXD];
+    memset(C, 0, sizeof(C));
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+            for (int p = 0; p < n; ++p) s += al[p] * (v[(size_t)p * D + i] - mean[i]) * (v[(size_t)p * D + j] - mean[j]);
+            C[i][j] = s / W;
+        }
+    double trC = 0.0;
+    for (int i = 0; i < D; ++i) trC += C[i][i];
+    /* centred velocities and weights normalised so that sum a = N = n
+     * (the paper takes sum alpha_p = N, eq. lnL-GM) */
+    const double N = (double)n;
+    for (int p = 0; p < n; ++p) {
+        a[p] = al[p] * (double)n / W;
+        for (int i = 0; i < D; ++i) x[(size_t)p * D + i] = v[(size_t)p * D + i] - mean[i];
+    }
+
+    /* O2: too few particles (the paper asks for more than ~10 per cell) or a
+     * singular covariance: a single Gaussian with the cell's own moments. */
+    double LC[ORC_MAXD][ORC_MAXD];
+    int c_spd = chol(D, (const double(*)[ORC_MAXD])C, LC) == 0;
+    int have_init = J->init_K != NULL && J->init_K[c] > 0;
+    if (n <= J->n_min || !c_spd) {
+        m.K = 1;
+        m.w[0] = 1.0;
+        memcpy(m.S[0], C, sizeof(C));
+        memcpy(m.L[0], LC, sizeof(LC));
+        status |= c_spd ? ORC_SMALL_CELL_K1 : (ORC_SMALL_CELL_K1 | ORC_DEGENERATE);
+        if (c_spd) {
+            double Lk = penalised_L(D, T, &m, n, x, a, N);
+            J->L_pen[c] = Lk;
+            J->L_final[c] = Lk;
+        } else {
+            J->L_pen[c] = -INFINITY;
+            J->L_final[c] = -INFINITY;
+        }
+        write_mixture(J, c, &m, mean);
+        J->status[c] = status;
+        return;
+    }
+
+    if (have_init) {
+        /* supplied initial mixture (learned warm start or a test's fixed init) */
+        int K0 = J->init_K[c];
+        if (K0 > J->kmax) K0 = J->kmax;
+        m.K = K0;
+        for (int k = 0; k < K0; ++k) {
+            size_t s = (size_t)c * J->kmax + k;
+            m.w[k] = J->init_w[s];
+            for (int i = 0; i < D; ++i) m.mu[k][i] = J->init_mu[s * D + i] - mean[i];
+            unpack_sym(D, J->init_S + s * nt, m.S[k]);
+            if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+        }
+        renormalise(&m);
+    } else {
+        /* O3: cold start (Sec. 2.3): K0 components, each mean at a distinct
+         * randomly chosen particle, each covariance the whole cell's covariance,
+         * equal weights.  K0 is capped so that N - T K0 / 2 > 0 in eq. (omegak). */
+        int K0 = J->kmax < n ? J->kmax : n;
+        if (T > 0.0) {
+            double cap = floor(N / T);
+            if (cap < 1.0) cap = 1.0;
+            if ((double)K0 > cap) {
+                K0 = (int)cap;
+                status |= ORC_K0_CAPPED;
+            }
+        }
+        /* partial Fisher-Yates over particle indices; draw j uses Philox with
+         * key (seed, "INIT") and counter (j, cell, 0, 0); the index offset is
+         * floor(x * (n - j) / 2^64) of the first 64-bit output x. */
+        int* perm = (int*)malloc(sizeof(int) * (size_t)n);
+        orc_init_indices(n, K0, J->seed, (uint64_t)c, perm);
+        m.K = K0;
+        for (int k = 0; k < K0; ++k) {
+            m.w[k] = 1.0 / K0;
+            for (int i = 0; i < D; ++i) m.mu[k][i] = x[(size_t)perm[k] * D + i];
+            memcpy(m.S[k], C, sizeof(C));
+            memcpy(m.L[k], LC, sizeof(LC));
+        }
+        free(perm);
+    }
+
+    /* O4-O6: component-wise adaptive EM sweeps (Sec. 2.3 steps 1-4) */
+    const int fixed = J->fixed_sweeps ? J->fixed_sweeps[c] : 0;
+    const int standard = (J->mode & ORC_MODE_STANDARD_EM) != 0;
+    const int cap_sweeps = fixed > 0 ? fixed : J->max_sweeps;
+    double L_prev = 0.0, L_s = 0.0;
+    int s = 0;
+    int64_t visits = 0;
+    const double half_T = 0.5 * T;
+    for (s = 1; s <= cap_sweeps; ++s) {
+        int annihilated = 0;
+        if (standard) {
+            /* plain EM: joint E-step, then every component's M-step with
+             * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
+            double* gk = g;
+            mixture next = m;
+            double ell[ORC_MAXK];
+            for (int p = 0; p < n; ++p) {
+                double lse = mixture_lse(D, &m, x + (size_t)p * D, ell);
+                for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = a[p] * exp(ell[k] - lse);
+            }
+            for (int k = 0; k < m.K; ++k) {
+                double Nk = 0.0;
+                for (int p = 0; p < n; ++p) Nk += gk[(size_t)k * n + p];
+                mean_cov(D, n, x, gk + (size_t)k * n, Nk, next.mu[k], next.S[k]);
+                next.w[k] = Nk / N;
+                if (factor_component(D, &next, k, trC)) status |= ORC_COV_FLOOR;
+            }
+            visits += m.K;
+            m = next;
+        } else {
+            int k = 0;
+            while (k < m.K) {
+                /* step 1: E-step for component k with the current parameters */
+                responsibilities(D, &m, k, n, x, a, g);
+                double Nk = 0.0;
+                for (int p = 0; p < n; ++p) Nk += g[p];
+                ++visits;
+                if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
+                /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
+                if (Nk - half_T <= 0.0) {
+                    remove_component(&m, k);
+                    renormalise(&m);
+                    annihilated = 1;
+                    continue;
+                }
+                mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
+                /* eq. (omegak) with K the current number of live components */
+                m.w[k] = (Nk - half_T) / (N - half_T * m.K);
+                /* step 3: renormalise */
+                renormalise(&m);
+                if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+                ++k;
+            }
+        }
+        /* step 4: monitor the penalised log-likelihood */
+        L_s = penalised_L(D, T, &m, n, x, a, N);
+        if (J->L_trace) J->L_trace[(size_t)c * J->max_sweeps + (s - 1)] = L_s;
+        if (J->K_trace) J->K_trace[(size_t)c * J->max_sweeps + (s - 1)] = m.K;
+        if (fixed > 0) {
+            if (s == fixed) break;
+            L_prev = L_s;
+            continue;
+        }
+        if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
+        if (s == J->max_sweeps) {
+            status |= ORC_MAXSWEEPS;
+            break;
+        }
+        L_prev = L_s;
+    }
+    if (s > cap_sweeps) s = cap_sweeps;
+    J->sweeps[c] = s;
+    J->visits[c] = visits;
+    J->L_pen[c] = L_s;
+
+    /* O7: one unpenalised joint step restores exact moments (Sec. 2.3.1) */
+    if ((J->mode & ORC_MODE_NO_FINISH) == 0 && mle_finish(D, &m, n, x, a, N, g) != 0) {
+        /* degenerate output: fall back to the single-Gaussian closed form */
+        m.K = 1;
+        m.w[0] = 1.0;
+        memcpy(m.S[0], C, sizeof(C));
+        memcpy(m.L[0], LC, sizeof(LC));
+        memset(m.mu[0], 0, sizeof(m.mu[0]));
+        status |= ORC_DEGENERATE;
+    }
+    /* O8: penalised L at the output parameters */
+    J->L_final[c] = penalised_L(D, T, &m, n, x, a, N);
+    write_mixture(J, c, &m, mean);
+    J->status[c] = status;
+}
+
+typedef struct {
+    const compress_job* J;
+    int64_t c0, c1;
+} compress_chunk;
+
+static int64_t max_cell_len(const int64_t* off, int64_t c0, int64_t c1)
+{
+    int64_t mx = 0;
+    for (int64_t c = c0; c < c1; ++c)
+        if (off[c + 1] - off[c] > mx) mx = off[c + 1] - off[c];
+    return mx;
+}
+
+static void* compress_worker(void* arg)
+{
+    compress_chunk* ch = (compress_chunk*)arg;
+    const compress_job* J = ch->J;
+    int64_t nmax = max_cell_len(J->off, ch->c0, ch->c1);
+    if (nmax < 1) nmax = 1;
+    double* x = (double*)malloc(sizeof(double) * (size_t)nmax * J->D);
+    double* a = (double*)malloc(sizeof(double) * (size_t)nmax);
+    double* g = (double*)malloc(sizeof(double) * (size_t)nmax * ORC_MAXK);
+    for (int64_t c = ch->c0; c < ch->c1; ++c) compress_cell(J, c, x, a, g);
+    free(x);
+    free(a);
+    free(g);
+    return NULL;
+}
+
+static void run_chunks(int64_t n_cells, int nthreads, void* (*fn)(void*), void* job, size_t chunk_size,
+                       void (*fill)(void* chunk, void* job, int64_t c0, int64_t c1))
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > n_cells) nthreads = n_cells > 0 ? (int)n_cells : 1;
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
+    char* chunks = (char*)malloc(chunk_size * nthreads);
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t c0 = n_cells * t / nthreads, c1 = n_cells * (t + 1) / nthreads;
+        fill(chunks + chunk_size * t, job, c0, c1);
+    }
+    if (nthreads == 1) {
+        fn(chunks);
+    } else {
+        for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, fn, chunks + chunk_size * t);
+        for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    }
+    free(th);
+    free(chunks);
+}
+
+static void fill_compress(void* chunk, void* job, int64_t c0, int64_t c1)
+{
+    compress_chunk* ch = (compress_chunk*)chunk;
+    ch->J = (const compress_job*)job;
+    ch->c0 = c0;
+    ch->c1 = c1;
+}
+
+int orc_compress(const double* v, const double* alpha, const int64_t* off, int64_t n_cells, int D, int kmax,
+                 int n_min, int max_sweeps, const int32_t* fixed_sweeps, double tol, uint64_t seed, int mode,
+                 double T_override, const int32_t* init_K, const double* init_w, const double* init_mu,
+                 const double* init_S, int32_t* K, double* w, double* mu, double* S, double* mom, double* L_pen,
+                 double* L_final, int32_t* sweeps, int32_t* status, int64_t* visits, double* L_trace,
+                 int32_t* K_trace, int nthreads)
+{
+    if (D < 1 || D > ORC_MAXD || kmax < 1 || kmax > ORC_MAXK || max_sweeps < 1) return -1;
+    compress_job J = {v, alpha, off, n_cells, D, kmax, n_min, max_sweeps, fixed_sweeps, tol, seed, mode, T_override,
+                      init_K, init_w, init_mu, init_S, K, w, mu, S, mom, L_pen, L_final, sweeps, status, visits,
+                      L_trace, K_trace};
+    run_chunks(n_cells, nthreads, compress_worker, &J, sizeof(compress_chunk), fill_compress);
+    return 0;
+}
+
+/* Unpenalised joint finish applied to an arbitrary mixture (test entry for
+ * the conservation property of Sec. 2.3.1). Mixture arrays are in and out;
+ * mu in original coordinates. Returns 0 or -1 if a covariance is not SPD. */
+int orc_mle_finish(const double* v, const double* alpha, int n, int D, int K, double* w, double* mu, double* S)
+{
+    if (n < 1 || D < 1 || D > ORC_MAXD || K < 1 || K > ORC_MAXK) return -1;
+    double W = 0.0;
+    for (int p = 0; p < n; ++p) W += alpha[p];
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* g = (double*)malloc(sizeof(double) * (size_t)n * K);
+    for (int p = 0; p < n; ++p) a[p] = alpha[p] * n / W;
+    mixture m;
+    memset(&m, 0, sizeof(m));
+    m.K = K;
+    int nt = ntri(D);
+    for (int k = 0; k < K; ++k) {
+        m.w[k] = w[k];
+        for (int i = 0; i < D; ++i) m.mu[k][i] = mu[k * D + i];
+        unpack_sym(D, S + k * nt, m.S[k]);
+        if (chol(D, (const double(*)[ORC_MAXD])m.S[k], m.L[k]) != 0) {
+            free(a);
+            free(g);
+            return -1;
+        }
+    }
+    int rc = mle_finish(D, &m, n, v, a, (double)n, g);
+    if (rc == 0)
+        for (int k = 0; k < K; ++k) {
+            w[k] = m.w[k];
+            for (int i = 0; i < D; ++i) mu[k * D + i] = m.mu[k][i];
+            pack_sym(D, (const double(*)[ORC_MAXD])m.S[k], S + k * nt);
+        }
+    free(a);
+    free(g);
+    return rc;
+}
+
+/* Penalised log-likelihood of a given mixture on given particles (weights
+ * normalised to sum n), eq. (lnL-GM).  T < 0 selects D(D+3)/2. */
+double orc_penalised_L(const double* v, const double* alpha, int n, int D, int K, const double* w, const double* mu,
+                       const double* S, double T)
+{
+    if (T < 0.0) T = 0.5 * D * (D + 3);
+    double W = 0.0;
+    for (int p = 0; p < n; ++p) W += alpha[p];
+    double* a = (double*)malloc(sizeof(double) * n);
+    for (int p = 0; p < n; ++p) a[p] = alpha[p] * n / W;
+    mixture m;
+    memset(&m, 0, sizeof(m));
+    m.K = K;
+    int nt = ntri(D);
+    for (int k = 0; k < K; ++k) {
+        m.w[k] = w[k];
+        for (int i = 0; i < D; ++i) m.mu[k][i] = mu[k * D + i];
+        unpack_sym(D, S + k * nt, m.S[k]);
+        if (chol(D, (const double(*)[ORC_MAXD])m.S[k], m.L[k]) != 0) {
+            free(a);
+            return NAN;
+        }
+    }
+    double L = penalised_L(D, T, &m, n, v, a, (double)n);
+    free(a);
+    return L;
+}
+
+/* ------------------------------------------------------------------ */
+/* reconstruct: ancestral sampling (Sec. 2.4) + Lemons projection      */
+/* (Sec. 2.4.2, eqs. alpha/beta)                                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const int32_t* K;
+    const double* w;
+    const double* mu;
+    const double* S;
+    int kmax;
+    const int64_t* out_off;
+    const double* target; /* W, P[D], E per cell */
+    int64_t n_cells;
+    int D, dx;
+    uint64_t seed;
+    double* v_out;
+    double* w_out;
+    double* x_out;
+    int32_t* status;
+    double* stats; /* nullable: [n_cells * 4] = a (scale), N', |p'|, E' */
+} recon_job;
+
+/* uniform number j (0-based) of particle i in cell c:
+ * block b = j / 4 of Philox with key (seed, "RECO") and counter (i, c, b, 0) */
+static void particle_uniforms(uint64_t seed, int64_t c, int64_t i, int count, double* u)
+{
+    uint64_t key[2] = {seed, ORC_TAG_RECON};
+    for (int b = 0; b * 4 < count; ++b) {
+        uint64_t ctr[4] = {(uint64_t)i, (uint64_t)c, (uint64_t)b, 0}, r[4];
+        orc_philox4x64_10(ctr, key, r);
+        for (int t = 0; t < 4 && 4 * b + t < count; ++t) u[4 * b + t] = u53(r[t]);
+    }
+}
+
+static void reconstruct_cell(const recon_job* J, int64_t c)
+{
+    const int D = J->D, nt = ntri(D), dx = J->dx;
+    const int64_t o0 = J->out_off[c], o1 = J->out_off[c + 1];
+    const int64_t n = o1 - o0;
+    int32_t st = 0;
+    const double* tg = J->target + (size_t)c * (2 + D);
+    if (J->stats)
+        for (int i = 0; i < 4; ++i) J->stats[(size_t)c * 4 + i] = 0.0;
+    int K = J->K[c];
+    if (n == 0) {
+        J->status[c] = 0;
+        return;
+    }
+    if (K < 1 || K > J->kmax) {
+        J->status[c] = ORC_DEGENERATE;
+        for (int64_t i = 0; i < n; ++i) {
+            for (int d = 0; d < D; ++d) J->v_out[(size_t)(o0 + i) * D + d] = 0.0;
+            J->w_out[o0 + i] = 0.0;
+            for (int d = 0; d < dx; ++d) J->x_out[(size_t)(o0 + i) * dx + d] = 0.0;
+        }
+        return;
+    }
+    /* R1: Cholesky factors and cumulative weights (c_{K-1} := 1) */
+    double L[ORC_MAXK][ORC_MAXD][ORC_MAXD], cum[ORC_MAXK];
+    double run = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double Sk[ORC_MAXD][ORC_MAXD];
+        unpack_sym(D, J->S + ((size_t)c * J->kmax + k) * nt, Sk);
+        if (chol(D, (const double(*)[ORC_MAXD])Sk, L[k]) != 0) {
+            /* singular component: sample its mean only */
+            memset(L[k], 0, sizeof(L[k]));
+            st |= ORC_DEGENERATE;
+        }
+        run += J->w[(size_t)c * J->kmax + k];
+        cum[k] = run;
+    }
+    cum[K - 1] = 1.0;
+    const double W = tg[0];
+    const double wp = W / (double)n; /* equal weights (Sec. 2.4) */
+    const int nu = 1 + 2 * ((D + 1) / 2) + dx;
+    /* R2: ancestral sampling: component by inverse CDF, then v = mu_k + L_k z
+     * with Box-Muller normals; positions uniform in the cell. */
+    for (int64_t i = 0; i < n; ++i) {
+        double u[8];
+        particle_uniforms(J->seed, c, i, nu, u);
+        int k = 0;
+        while (k < K - 1 && !(u[0] < cum[k])) ++k;
+        double z[4];
+        for (int pr = 0; pr < (D + 1) / 2; ++pr) {
+            double r = sqrt(-2.0 * log(1.0 - u[1 + 2 * pr]));
+            double th = TWO_PI * u[2 + 2 * pr];
+            z[2 * pr] = r * cos(th);
+            z[2 * pr + 1] = r * sin(th);
+        }
+        const double* mk = J->mu + ((size_t)c * J->kmax + k) * D;
+        for (int d = 0; d < D; ++d) {
+            double s = mk[d];
+            for (int e = 0; e <= d; ++e) s += L[k][d][e] * z[e];
+            J->v_out[(size_t)(o0 + i) * D + d] = s;
+        }
+        J->w_out[o0 + i] = wp;
+        for (int d = 0; d < dx; ++d) J->x_out[(size_t)(o0 + i) * dx + d] = u[1 + 2 * ((D + 1) / 2) + d];
+    }
+    /* R3: moments of the sample */
+    double Np = 0.0, pp[ORC_MAXD] = {0, 0, 0}, Ep = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* vi = J->v_out + (size_t)(o0 + i) * D;
+        double wi = J->w_out[o0 + i];
+        Np += wi;
+        for (int d = 0; d < D; ++d) {
+            pp[d] += wi * vi[d];
+            Ep += 0.5 * wi * vi[d] * vi[d];
+        }
+    }
+    /* R4: scale a and shift beta, eq. (alpha):
+     *   a = sqrt((2 E N' - |P|^2) / (2 E' N' - |p'|^2)),  beta = (P - a p') / (a N') */
+    double E = tg[1 + D];
+    double P2 = 0.0, pp2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+        P2 += tg[1 + d] * tg[1 + d];
+        pp2 += pp[d] * pp[d];
+    }
+    double num = 2.0 * E * Np - P2;
+    double den = 2.0 * Ep * Np - pp2;
+    double scale = 0.0;
+    if (num > 0.0 && den > 0.0) {
+        scale = sqrt(num / den);
+        double beta[ORC_MAXD];
+        for (int d = 0; d < D; ++d) beta[d] = (tg[1 + d] - scale * pp[d]) / (scale * Np);
+        for (int64_t i = 0; i < n; ++i) {
+            double* vi = J->v_out + (size_t)(o0 + i) * D;
+            for (int d = 0; d < D; ++d) vi[d] = scale * (vi[d] + beta[d]);
+        }
+    } else {
+        /* R5: the projection has no real solution; leave the sample as drawn */
+        st |= ORC_LEMONS_SKIPPED;
+    }
+    if (J->stats) {
+        J->stats[(size_t)c * 4 + 0] = scale;
+        J->stats[(size_t)c * 4 + 1] = Np;
+        J->stats[(size_t)c * 4 + 2] = sqrt(pp2);
+        J->stats[(size_t)c * 4 + 3] = Ep;
+    }
+    J->status[c] = st;
+}
+
+typedef struct {
+    const recon_job* J;
+    int64_t c0, c1;
+} recon_chunk;
+
+static void* recon_worker(void* arg)
+{
+    recon_chunk* ch = (recon_chunk*)arg;
+    for (int64_t c = ch->c0; c < ch->c1; ++c) reconstruct_cell(ch->J, c);
+    return NULL;
+}
+
+static void fill_recon(void* chunk, void* job, int64_t c0, int64_t c1)
+{
+    recon_chunk* ch = (recon_chunk*)chunk;
+    ch->J = (const recon_job*)job;
+    ch->c0 = c0;
+    ch->c1 = c1;
+}
+
+int orc_reconstruct(const int32_t* K, const double* w, const double* mu, const double* S, int kmax,
+                    const int64_t* out_off, const double* target, int64_t n_cells, int D, int dx, uint64_t seed,
+                    double* v_out, double* w_out, double* x_out, int32_t* status, double* stats, int nthreads)
+{
+    if (D < 1 || D > ORC_MAXD || dx < 0 || dx > 3 || kmax < 1 || kmax > ORC_MAXK) return -1;
+    recon_job J = {K, w, mu, S, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out, status, stats};
+    run_chunks(n_cells, nthreads, recon_worker, &J, sizeof(recon_chunk), fill_recon);
+    return 0;
+}
