@@ -842,7 +842,10 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
     double num = 2.0 * E * Np - P2;
     double den = 2.0 * Ep * Np - pp2;
     double scale = 0.0;
-    if (num > 0.0 && den > 0.0) {
+    /* Each bracket is a difference of two terms of size 2 E N'; it vanishes
+     * exactly when all velocities coincide (the denominator for n' = 1), so a
+     * value within rounding of zero (1e-12 of either term) counts as zero. */
+    if (num > 1e-12 * (2.0 * E * Np) && den > 1e-12 * (2.0 * Ep * Np)) {
         scale = sqrt(num / den);
         double beta[ORC_MAXD];
         for (int d = 0; d < D; ++d) beta[d] = (tg[1 + d] - scale * pp[d]) / (scale * Np);

@@ -1,0 +1,87 @@
+"""ctypes view of libgmcr.so (the C ABI in include/gmcr.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation behind these bindings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmcr.so")
+
+GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL = 0, -1, -2, -3, -4
+
+STATUS = {
+    "SMALL_CELL_K1": 1 << 0, "K0_CAPPED": 1 << 1, "COV_FLOOR": 1 << 2, "MAXSWEEPS": 1 << 3,
+    "NEAR_TIE": 1 << 4, "WARM_FALLBACK": 1 << 5, "NONFINITE_INPUT": 1 << 6,
+    "LEMONS_SKIPPED": 1 << 7, "DEGENERATE": 1 << 8,
+}
+
+P = ctypes.c_void_p
+
+
+class GmOpts(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int32), ("kmax", ctypes.c_int32), ("n_min", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32), ("tol_rel", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("estep_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class GmMix(ctypes.Structure):
+    _fields_ = [(n, P) for n in ("K", "omega", "mu", "sigma", "moments", "L_pen", "L_final", "sweeps", "status",
+                                 "visits")]
+
+
+class GmInit(ctypes.Structure):
+    _fields_ = [(n, P) for n in ("K", "omega", "mu", "sigma")]
+
+
+EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_reconstruct_workspace",
+           "gm_reconstruct", "gm_profile_enable", "gm_profile_read", "gm_strerror", "gm_version")
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def load():
+    """Load libgmcr.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing("libgmcr.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    L.gm_opts_default.argtypes = [ctypes.POINTER(GmOpts), ctypes.c_int32, ctypes.c_int32]
+    L.gm_opts_default.restype = None
+    L.gm_compress_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(GmOpts)]
+    L.gm_compress_workspace.restype = ctypes.c_size_t
+    L.gm_compress.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmInit),
+                              ctypes.POINTER(GmMix), P, ctypes.c_size_t, P]
+    L.gm_compress.restype = ctypes.c_int
+    L.gm_reconstruct_workspace.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    L.gm_reconstruct_workspace.restype = ctypes.c_size_t
+    L.gm_reconstruct.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_uint64, P, P, P, P, P, ctypes.c_size_t, P]
+    L.gm_reconstruct.restype = ctypes.c_int
+    L.gm_profile_enable.argtypes = [ctypes.c_int]
+    L.gm_profile_enable.restype = None
+    L.gm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.gm_profile_read.restype = ctypes.c_int
+    L.gm_strerror.argtypes = [ctypes.c_int]
+    L.gm_strerror.restype = ctypes.c_char_p
+    L.gm_version.argtypes = []
+    L.gm_version.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc, what):
+    if rc != GM_OK:
+        msg = load().gm_strerror(rc).decode()
+        raise RuntimeError("%s failed: %s (%d)" % (what, msg, rc))

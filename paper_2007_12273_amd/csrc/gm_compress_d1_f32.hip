@@ -1,0 +1,20 @@
+// Instantiates the EM kernels for D = 1 with float iterations.
+#include "gm_compress_impl.h"
+
+namespace gm {
+
+int launch_compress_d1_float(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+{
+    return launch_bucket_dr<1, float>(kmax_tpl, bucket, a, grid, st);
+}
+
+int grid_compress_d1_float(int kmax_tpl, int bucket) { return grid_dr<1, float>(kmax_tpl, bucket); }
+
+int launch_compress_pre_d1(const CompressArgs& a, hipStream_t st) { return launch_pre_dr<1>(a, st); }
+
+int launch_compress_finish_d1(int kmax_tpl, const CompressArgs& a, hipStream_t st)
+{
+    return launch_finish_dr<1>(kmax_tpl, a, st);
+}
+
+}  // namespace gm

@@ -1,0 +1,13 @@
+// Instantiates the EM kernels for D = 1 with double iterations.
+#include "gm_compress_impl.h"
+
+namespace gm {
+
+int launch_compress_d1_double(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+{
+    return launch_bucket_dr<1, double>(kmax_tpl, bucket, a, grid, st);
+}
+
+int grid_compress_d1_double(int kmax_tpl, int bucket) { return grid_dr<1, double>(kmax_tpl, bucket); }
+
+}  // namespace gm

@@ -1,0 +1,1103 @@
+// gm_compress_impl.h -- per-cell adaptive EM-GM for gfx950.
+//
+// Three kernels per compress call (plus the length-bucket plan):
+//   k_moments  one workgroup per cell, FP64: W = sum alpha, P = sum alpha v,
+//              S = sum alpha v v^T, mean m = P / W, covariance C about m (two
+//              passes); classifies the cell (invalid / empty / small or
+//              singular -> closed form / EM) and bins EM cells by length.
+//   k_em       the hot loop.  Persistent workgroups pull cells of one length
+//              bucket from a queue.  Centred FP32 velocities, normalised
+//              weights and every (particle, component) density term stay in
+//              VGPRs for the whole fit; LDS carries only the component
+//              parameters and the cross-wave partial sums.  Writes the
+//              converged penalised mixture into the output record.
+//   k_finish   one workgroup per cell, FP64: the unpenalised joint EM step
+//              (Sec. 2.3.1) or the single-Gaussian closed form, then the
+//              penalised log-likelihood of the output mixture.
+//
+// EM arithmetic per cell (Sec. 2.3 of the paper):
+//   start   cold: min(kmax, n, floor(N/T)) distinct particles (Philox partial
+//           Fisher-Yates) as means, C as covariances, equal weights; or a
+//           supplied warm-start mixture
+//   sweep   for each live component k in slot order:
+//             E-step  gamma_pk = a_p e_pk / sum_j e_pj            (eq. responsibility)
+//             M-step  N_k, mu_k, Sigma_k about the new mean       (eqs. muk, sigmak)
+//             remove k if N_k - T/2 <= 0                          (eq. omegak)
+//             else w_k = (N_k - T/2)/(N - T K/2), renormalise     (eq. omegak, step 3)
+//           then the penalised log-likelihood (eq. lnL-GM) and the stop test
+//
+// Density terms are kept relative to a per-particle reference in base 2:
+//   e_pj = 2^(c_j - |A_j (x_p - mu_j)|^2 - ref_p),
+//   c_j  = log2 u_j - D/2 log2(2 pi) - log2 sqrt(det Sigma_j),
+//   A_j  = sqrt(log2(e)/2) L_j^{-1},   Sigma_j = L_j L_j^T,
+// with u_j unnormalised weights (G = sum u_j).  A component update costs one
+// exp2 per particle; the denominator sum_j e_pj is re-summed from the stored
+// terms, so no cancellation builds up.  At the end of every sweep ref_p
+// absorbs log2 of the particle's mixture density, which is the per-particle
+// term of eq. (lnL-GM).
+#pragma once
+
+#include "gm_device.h"
+#include "gm_launch.h"
+
+namespace gm {
+
+// per-cell record written by k_moments, read by k_em and k_finish
+template <int D>
+struct CellInfo {
+    double m[D];        // mean
+    double C[ntri(D)];  // covariance about the mean (packed)
+    double trC;
+    double W;           // sum of weights
+    int32_t kind;       // CELL_*
+    int32_t n;
+};
+
+enum { CELL_EM = 0, CELL_CLOSED = 1, CELL_INVALID = 2, CELL_EMPTY = 3, CELL_OVERSIZE = 4 };
+
+struct CompressArgs {
+    const double* v;
+    const double* alpha;
+    const int64_t* off;
+    int64_t n_cells;
+    void* cells;             // CellInfo<D>[n_cells]
+    int32_t* list;           // bucketed EM cells
+    int32_t* init_idx;       // [n_cells * kInitSlots] cold-start particle indices
+    int32_t* plan;           // PLAN_* layout
+    int32_t bucket;
+    int32_t nwaves;
+    int32_t kmax, n_min, max_sweeps;
+    double tol;
+    uint64_t seed;
+    const int32_t* fixed;    // nullable
+    gm_init init;            // init.K == nullptr: cold start
+    gm_mix out;
+};
+
+enum { PLAN_COUNT = 0, PLAN_BASE = 16, PLAN_CURSOR = 32, PLAN_QUEUE = 48, PLAN_SIZE = 64 };
+constexpr int kInitSlots = 16;
+
+constexpr double kSqrtHalfLog2e = 0.84932180028801904272;  // sqrt(log2(e) / 2)
+constexpr double kLog2TwoPi = 2.6514961294723187980;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLnTwoPi = 1.8378770664093454836;
+
+__host__ __device__ inline int bucket_of(int n)
+{
+    for (int b = 0; b < kNumBuckets; ++b)
+        if (n <= kBuckets8[b].max_n) return b;
+    return -1;
+}
+
+// ===========================================================================
+// k_moments
+// ===========================================================================
+template <int D>
+__global__ __launch_bounds__(256) void k_moments(CompressArgs A)
+{
+    constexpr int NT = ntri(D);
+    constexpr int NM = nmom(D);
+    __shared__ double red[2 * kMaxWaves * (NM + 1)];
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x, nthreads = blockDim.x, nwaves = nthreads >> 6;
+    int par = 0;
+    const int64_t o0 = A.off[c];
+    const int64_t n64 = A.off[c + 1] - o0;
+    CellInfo<D>* ci = static_cast<CellInfo<D>*>(A.cells) + c;
+    double* mom = A.out.moments + (size_t)c * NM;
+    if (n64 <= 0 || n64 > kMaxCellParticles) {
+        if (tid < NM) mom[tid] = 0.0;
+        if (tid == 0) {
+            ci->kind = n64 == 0 ? CELL_EMPTY : CELL_OVERSIZE;
+            ci->n = 0;
+        }
+        return;
+    }
+    const int n = (int)n64;
+    const double* vc = A.v + o0 * D;
+    const double* ac = A.alpha + o0;
+    double acc[NM + 1];
+#pragma unroll
+    for (int t = 0; t < NM + 1; ++t) acc[t] = 0.0;
+    for (int i = tid; i < n; i += nthreads) {
+        const double al = ac[i];
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = vc[(size_t)i * D + d];
+        bool bad = !isfinite(al) || !(al > 0.0);
+#pragma unroll
+        for (int d = 0; d < D; ++d) bad |= !isfinite(x[d]);
+        acc[NM] += bad ? 1.0 : 0.0;
+        acc[0] += al;
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[1 + d] += al * x[d];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) acc[1 + D + tri_idx<D>(a, b)] += al * x[a] * x[b];
+    }
+    block_sum<NM + 1>(acc, red, par, nwaves);
+    if (acc[NM] > 0.0) {
+        if (tid < NM) mom[tid] = 0.0;
+        if (tid == 0) {
+            ci->kind = CELL_INVALID;
+            ci->n = n;
+        }
+        return;
+    }
+    if (tid < NM) mom[tid] = acc[tid];
+    const double W = acc[0];
+    double m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = acc[1 + d] / W;
+    double cov[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cov[t] = 0.0;
+    for (int i = tid; i < n; i += nthreads) {
+        const double al = ac[i];
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = vc[(size_t)i * D + d] - m[d];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) cov[tri_idx<D>(a, b)] += al * x[a] * x[b];
+    }
+    block_sum<NM + 1>(cov, red, par, nwaves);
+    if (tid == 0) {
+        double C[NT], L[NT], tr = 0.0;
+        for (int t = 0; t < NT; ++t) C[t] = cov[t] / W;
+        for (int d = 0; d < D; ++d) tr += C[tri_idx<D>(d, d)];
+        const bool spd = chol<D, double>(C, L);
+        for (int d = 0; d < D; ++d) ci->m[d] = m[d];
+        for (int t = 0; t < NT; ++t) ci->C[t] = C[t];
+        ci->trC = tr;
+        ci->W = W;
+        ci->n = n;
+        const bool closed = n <= A.n_min || !spd;
+        ci->kind = closed ? CELL_CLOSED : CELL_EM;
+        if (!closed) {
+            atomicAdd(&A.plan[PLAN_COUNT + bucket_of(n)], 1);
+            // cold start: min(kmax, n, floor(N/T)) distinct particles by a
+            // partial Fisher-Yates draw; draw j swaps positions j and
+            // j + floor(x (n - j) / 2^64), x the first word of Philox with key
+            // (seed, "INIT") and counter (j, cell, 0, 0).  The permutation is
+            // kept as a sparse record of the swapped positions.
+            const double T = 0.5 * D * (D + 3);
+            int K = min(A.kmax, n);
+            const int cap = max(1, (int)floor((double)n / T));
+            if (K > cap) K = cap;
+            int pos[2 * kInitSlots], val[2 * kInitSlots], nrec = 0;
+            for (int j = 0; j < K; ++j) {
+                const u64x4 r = philox4x64_10((uint64_t)j, (uint64_t)c, 0, 0, A.seed, kTagInit);
+                const int rr = j + (int)__umul64hi(r.x, (uint64_t)(n - j));
+                int vr = rr, vj = j, tr = -1, tj = -1;
+                for (int t = 0; t < nrec; ++t) {
+                    if (pos[t] == rr) {
+                        vr = val[t];
+                        tr = t;
+                    }
+                    if (pos[t] == j) {
+                        vj = val[t];
+                        tj = t;
+                    }
+                }
+                if (tj < 0) {
+                    tj = nrec++;
+                    pos[tj] = j;
+                }
+                val[tj] = vr;
+                if (rr != j) {
+                    if (tr < 0) {
+                        tr = nrec++;
+                        pos[tr] = rr;
+                    }
+                    val[tr] = vj;
+                }
+                A.init_idx[(size_t)c * kInitSlots + j] = vr;
+            }
+        }
+    }
+}
+
+// bucket bases and queue resets (one thread)
+static __global__ void k_plan_scan(int32_t* plan)
+{
+    int base = 0;
+    for (int b = 0; b < kNumBuckets; ++b) {
+        plan[PLAN_BASE + b] = base;
+        plan[PLAN_CURSOR + b] = 0;
+        plan[PLAN_QUEUE + b] = 0;
+        base += plan[PLAN_COUNT + b];
+    }
+}
+
+// EM cells into their buckets
+template <int D>
+__global__ void k_plan_scatter(CompressArgs A)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= A.n_cells) return;
+    const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+    if (ci->kind != CELL_EM) return;
+    const int b = bucket_of(ci->n);
+    const int pos = atomicAdd(&A.plan[PLAN_CURSOR + b], 1);
+    A.list[A.plan[PLAN_BASE + b] + pos] = (int32_t)c;
+}
+
+static __global__ void k_plan_reset(int32_t* plan)
+{
+    if (threadIdx.x < PLAN_SIZE) plan[threadIdx.x] = 0;
+}
+
+// ===========================================================================
+// k_em
+// ===========================================================================
+template <typename R, int D>
+struct CompState {
+    R mu[D];
+    R A[ntri(D)];   // sqrt(log2(e)/2) * inverse Cholesky factor, packed lower
+    R c2;           // log2 u + log2 sqrt det C - log2 sqrt det Sigma (C: cell covariance)
+    R S[ntri(D)];   // covariance (packed)
+    R u;            // unnormalised mixing weight
+};
+
+// Reciprocal and square root for the FP32 M-step: the hardware instructions
+// (about 1 ulp); FP64 keeps the correctly rounded operations.
+template <typename R>
+__device__ __forceinline__ R m_rcp(R x)
+{
+    if constexpr (std::is_same<R, float>::value)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return R(1) / x;
+}
+
+template <typename R>
+__device__ __forceinline__ R m_sqrt(R x)
+{
+    if constexpr (std::is_same<R, float>::value)
+        return __builtin_amdgcn_sqrtf(x);
+    else
+        return sqrt(x);
+}
+
+// Cholesky factor of a packed 1x1 / 3x3 covariance and the parameters of the
+// density term: A = sqrt(log2(e)/2) L^-1 and
+//   c2 = log2 u + log2 sqrt det C - log2 sqrt det Sigma
+// i.e. the log2 weighted density relative to the cell's own scale (C the
+// cell covariance, sdc = sqrt det C), so that exponent arguments stay O(1)
+// in FP32.  Returns false if S is not numerically positive definite.
+template <typename R, int D>
+__device__ __forceinline__ bool density_params(const R (&S)[ntri(D)], R u, R sdc, R (&Aout)[ntri(D)], R& c2)
+{
+    const R k = (R)kSqrtHalfLog2e;
+    if constexpr (D == 1) {
+        if (!(S[0] > R(0)) || !isfinite(S[0])) return false;
+        const R l00 = m_sqrt(S[0]);
+        const R i00 = m_rcp(l00);
+        Aout[0] = k * i00;
+        c2 = fast_log2(u * sdc * i00);
+        return true;
+    } else {
+        if (!(S[0] > R(0)) || !isfinite(S[0])) return false;
+        const R l00 = m_sqrt(S[0]);
+        const R i00 = m_rcp(l00);
+        const R l10 = S[1] * i00, l20 = S[2] * i00;
+        const R t11 = S[3] - l10 * l10;
+        if (!(t11 > R(0)) || !isfinite(t11)) return false;
+        const R l11 = m_sqrt(t11);
+        const R i11 = m_rcp(l11);
+        const R l21 = (S[4] - l20 * l10) * i11;
+        const R t22 = S[5] - l20 * l20 - l21 * l21;
+        if (!(t22 > R(0)) || !isfinite(t22)) return false;
+        const R l22 = m_sqrt(t22);
+        const R i22 = m_rcp(l22);
+        // inverse of the lower factor
+        const R m10 = -l10 * i00 * i11;
+        const R m21 = -l21 * i11 * i22;
+        const R m20 = -(l20 * i00 + l21 * m10) * i22;
+        Aout[0] = k * i00;
+        Aout[1] = k * m10;
+        Aout[2] = k * m20;
+        Aout[3] = k * i11;
+        Aout[4] = k * m21;
+        Aout[5] = k * i22;
+        c2 = fast_log2(u * (sdc * i00) * (i11 * i22));
+        return true;
+    }
+}
+
+// Factor a component, with the floor used when it fails (eps I, eps =
+// 1e-12 tr(C)/D, growing tenfold).  Returns true if the floor was needed.
+template <typename R, int D>
+__device__ __forceinline__ bool factor_comp(CompState<R, D>& cs, double trC, R sdc)
+{
+    if (density_params<R, D>(cs.S, cs.u, sdc, cs.A, cs.c2)) return false;
+    double eps = 1e-12 * trC / D;
+    for (int it = 0; it < 40; ++it) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) cs.S[tri_idx<D>(i, i)] += (R)eps;
+        if (density_params<R, D>(cs.S, cs.u, sdc, cs.A, cs.c2)) break;
+        eps *= 10.0;
+    }
+    return true;
+}
+
+template <typename R, int D>
+__device__ __forceinline__ R log2_term(const CompState<R, D>& cs, const R (&x)[D])
+{
+    R d[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) d[i] = x[i] - cs.mu[i];
+    return cs.c2 - tri_quad<D, R>(cs.A, d);
+}
+
+constexpr int kEmMaxWaves = kEmMaxThreads / 64;
+
+// sum of all slots of a density-term vector (unused and dead slots hold 0)
+template <typename V>
+__device__ __forceinline__ auto resum(const V& v) -> decltype(v[0] + v[0])
+{
+    constexpr int n = sizeof(V) / sizeof(v[0]);
+    auto s = v[0];
+#pragma unroll
+    for (int j = 1; j < n; ++j) s += v[j];
+    return s;
+}
+
+template <int D>
+__device__ __forceinline__ double sqrt_det(const double* C)
+{
+    if constexpr (D == 1) {
+        return sqrt(C[0]);
+    } else {
+        const double det = C[0] * (C[3] * C[5] - C[4] * C[4]) - C[1] * (C[1] * C[5] - C[4] * C[2]) +
+                           C[2] * (C[1] * C[4] - C[3] * C[2]);
+        return sqrt(det);
+    }
+}
+
+// P: particles per thread held in registers.  STORE_E: keep e_pj for every
+// (particle, slot) in registers; otherwise recompute the old term of the
+// updated component and track the denominator incrementally (large cells).
+//
+// Every wave keeps its own copy of the component parameters in LDS: all
+// threads compute the identical M-step, so a wave can publish an update to
+// its copy without waiting for the others.  The only workgroup barrier per
+// component update is the one inside the cross-wave reduction.
+template <int D, int KMAX, int P, bool STORE_E, typename R>
+__global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
+{
+    constexpr int NT = ntri(D);
+    constexpr int NS = 1 + D + NT;
+    const int nthreads = blockDim.x;
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    const double T = 0.5 * D * (D + 3);
+    const double halfT = 0.5 * T;
+
+    __shared__ CompressArgs A;   // arguments read where they are used, not pinned in SGPRs
+    __shared__ CompState<R, D> compw[kEmMaxWaves][KMAX];
+    __shared__ double red_d[2 * kMaxWaves * 2];
+    __shared__ R red_r[2 * kMaxWaves * NS];
+    __shared__ int s_idx;
+    __shared__ int s_flag;
+
+    if (tid == 0) A = A_in;
+    __syncthreads();
+    const int nwaves = A.nwaves;
+    const int bucket = A.bucket;
+    const int count = A.plan[PLAN_COUNT + bucket];
+    const int base = A.plan[PLAN_BASE + bucket];
+    int par_d = 0, par_r = 0;
+    CompState<R, D>* comp = compw[wid];
+
+    for (;;) {
+        if (tid == 0) s_idx = atomicAdd(&A.plan[PLAN_QUEUE + bucket], 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;
+        const int c = A.list[base + idx];
+        const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+        const int n = ci->n;
+        const double trC = ci->trC;
+        // sqrt det C: densities are kept relative to the cell's own scale
+        const double sdc64 = sqrt_det<D>(ci->C);
+        const R sdc = (R)sdc64;
+        const double lnc0 = -0.5 * D * kLnTwoPi - log(sdc64);
+        const int64_t o0 = A.off[c];
+        const double* vc = A.v + o0 * D;
+        const int kmax = A.kmax;
+        const double N = (double)n;
+        int32_t status = 0;
+
+        // ---------------- particles into registers --------------------------
+        R x[P][D], a[P], ref[P];
+        // density terms: one KMAX-vector per particle, indexed with the
+        // uniform slot number (register-indexed moves, no code per slot)
+        typedef R VecK __attribute__((ext_vector_type(KMAX)));
+        [[maybe_unused]] VecK e[STORE_E ? P : 1];
+        R Sden[P];  // sum_j e_pj, tracked incrementally and re-summed every sweep
+        {
+            const double wscale = N / ci->W;
+            double m[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) m[d] = ci->m[d];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const int i = tid + j * nthreads;
+                if (i < n) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x[j][d] = (R)(vc[(size_t)i * D + d] - m[d]);
+                    a[j] = (R)(A.alpha[o0 + i] * wscale);
+                } else {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x[j][d] = R(0);
+                    a[j] = R(0);
+                }
+                ref[j] = R(0);
+            }
+        }
+
+        // ---------------- initial mixture ------------------------------------
+        int K = 0;
+        const bool warm = A.init.K != nullptr && A.init.K[c] > 0;
+        if (tid == 0) s_flag = 0;
+        if (warm) {
+            K = min(A.init.K[c], kmax);
+        } else {
+            K = min(kmax, n);
+            const int cap = max(1, (int)floor(N / T));
+            if (K > cap) {
+                K = cap;
+                status |= GM_ST_K0_CAPPED;
+            }
+        }
+        __syncthreads();
+        if (tid < K) {
+            CompState<R, D> cs;
+            if (warm) {
+                const size_t s0 = (size_t)c * kmax;
+                double wsum = 0.0;
+                for (int j = 0; j < K; ++j) wsum += A.init.omega[s0 + j];
+                const size_t sk = s0 + tid;
+#pragma unroll
+                for (int d = 0; d < D; ++d) cs.mu[d] = (R)(A.init.mu[sk * D + d] - ci->m[d]);
+#pragma unroll
+                for (int q = 0; q < NT; ++q) cs.S[q] = (R)A.init.sigma[sk * NT + q];
+                cs.u = (R)(A.init.omega[sk] / wsum);
+            } else {
+                const int ip = A.init_idx[(size_t)c * kInitSlots + tid];
+#pragma unroll
+                for (int d = 0; d < D; ++d) cs.mu[d] = (R)(vc[(size_t)ip * D + d] - ci->m[d]);
+#pragma unroll
+                for (int q = 0; q < NT; ++q) cs.S[q] = (R)ci->C[q];
+                cs.u = (R)(1.0 / K);
+            }
+            if (factor_comp<R, D>(cs, trC, sdc)) s_flag = 1;
+            for (int w = 0; w < nwaves; ++w) compw[w][tid] = cs;
+        }
+        __syncthreads();
+        if (s_flag) status |= GM_ST_COV_FLOOR;
+        R G = R(0);
+        for (int j = 0; j < K; ++j) G += comp[j].u;
+
+        // ---------------- initial density terms ------------------------------
+        if constexpr (STORE_E) {
+            for (int j = 0; j < K; ++j) {
+                const CompState<R, D> cj = comp[j];
+#pragma unroll
+                for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                R mx = e[p][0];
+#pragma unroll
+                for (int j = 1; j < KMAX; ++j)
+                    if (j < K) mx = fmax(mx, e[p][j]);
+                ref[p] = mx;
+#pragma unroll
+                for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
+                Sden[p] = resum(e[p]);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                R mx = R(-1e30);
+                for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
+                R s = R(0);
+                for (int j = 0; j < K; ++j) s += fast_exp2(log2_term<R, D>(comp[j], x[p]) - mx);
+                ref[p] = mx;
+                Sden[p] = s;
+            }
+        }
+
+        // ---------------- sweeps ---------------------------------------------
+        const int fixed = A.fixed ? A.fixed[c] : 0;
+        const int max_sweeps = A.max_sweeps;
+        const double tol = A.tol;
+        const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
+        int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
+        uint32_t alive = (1u << K) - 1u;
+        double L_prev = 0.0, L_s = 0.0;
+        int s = 0;
+        long long visits = 0;
+        for (s = 1; s <= cap_sweeps; ++s) {
+            bool annihilated = false;
+            for (int k = 0; k < Kslots; ++k) {
+                if (!((alive >> k) & 1u)) continue;
+                ++visits;
+                R ckmu[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
+                const R cku = comp[k].u;
+                // E-step of k with the current parameters of every component,
+                // and the M-step sums about the current mean of k
+                R sums[NS];
+#pragma unroll
+                for (int t = 0; t < NS; ++t) sums[t] = R(0);
+                [[maybe_unused]] R eold[STORE_E ? 1 : P];
+                auto accumulate = [&](int p, R ek, R den) {
+                    const R inv = den > R(0) ? fast_rcp(den) : R(0);
+                    const R g = a[p] * ek * inv;
+                    R d[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
+                    sums[0] += g;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const R gd = g * d[i];
+                        sums[1 + i] += gd;
+#pragma unroll
+                        for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
+                    }
+                };
+                if constexpr (STORE_E) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
+                } else {
+                    const CompState<R, D> ck = comp[k];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
+                        accumulate(p, eold[p], Sden[p]);
+                    }
+                }
+                block_sum<NS>(sums, red_r, par_r, nwaves);
+                const R Nk = sums[0];
+                if (fabs((double)Nk - halfT) < 1e-5 * halfT) status |= GM_ST_NEAR_TIE;
+                if ((double)Nk - halfT <= 0.0) {
+                    // annihilate k (eq. omegak); the weights renormalise through G
+                    alive &= ~(1u << k);
+                    G -= cku;
+                    --K;
+                    annihilated = true;
+                    if constexpr (STORE_E) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const R s_old = Sden[p];
+                            const R s_new = s_old - e[p][k];
+                            e[p][k] = R(0);
+                            // a particle that lost most of its density: re-sum exactly
+                            Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const R s_old = Sden[p];
+                            R s_new = s_old - eold[p];
+                            if (!(s_new > R(1e-4) * s_old)) {
+                                s_new = R(0);
+                                for (int j = 0; j < Kslots; ++j)
+                                    if ((alive >> j) & 1u)
+                                        s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                            }
+                            Sden[p] = s_new;
+                        }
+                    }
+                    continue;
+                }
+                // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
+                CompState<R, D> cn;
+                const R invN = m_rcp(Nk);
+                R dl[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    dl[i] = sums[1 + i] * invN;
+                    cn.mu[i] = ckmu[i] + dl[i];
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = i; j < D; ++j)
+                        cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
+                const R wk = (R)(((double)Nk - halfT) / (N - halfT * K));
+                const R unew = wk * G;
+                G = G - cku + unew;
+                cn.u = unew;
+                if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
+                if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
+                if constexpr (STORE_E) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
+                        const R s_old = Sden[p];
+                        const R s_new = s_old - e[p][k] + enew;
+                        e[p][k] = enew;
+                        Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
+                        const R s_old = Sden[p];
+                        R s_new = s_old - eold[p] + enew;
+                        if (!(s_new > R(1e-4) * s_old)) {
+                            // the particle lost most of its density: re-sum exactly
+                            s_new = enew;
+                            for (int j = 0; j < Kslots; ++j)
+                                if (j != k && ((alive >> j) & 1u))
+                                    s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                        }
+                        Sden[p] = s_new;
+                    }
+                }
+            }
+
+            // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
+            const R lg2G = fast_log2(G);
+            double lsum[1] = {0.0};
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                R den;
+                if constexpr (STORE_E) {
+                    den = resum(e[p]);
+                } else {
+                    den = R(0);
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u)
+                            den += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                }
+                const R lg = fast_log2(den);
+                ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
+                lsum[0] += (double)a[p] * (double)ref[p];
+                if constexpr (STORE_E) {
+                    const R inv = fast_rcp(den);
+                    e[p] *= inv;  // unused slots hold 0
+                    Sden[p] = resum(e[p]);
+                } else {
+                    Sden[p] = R(1);
+                }
+            }
+            block_sum<2>(lsum, red_d, par_d, nwaves);
+            // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
+            if (lane < Kslots && ((alive >> lane) & 1u)) {
+                comp[lane].u = comp[lane].u * m_rcp(G);
+                comp[lane].c2 = comp[lane].c2 - lg2G;
+            }
+            R Gn = R(0);
+            double pen = 0.0;
+            for (int j = 0; j < Kslots; ++j)
+                if ((alive >> j) & 1u) Gn += comp[j].u;
+            for (int j = 0; j < Kslots; ++j)
+                if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
+            G = Gn;
+            const double dpar = K * T + K - 1;
+            // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
+            L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
+
+            // ---- compaction of dead slots (rare) ----
+            if (annihilated) {
+                for (int k = Kslots - 1; k >= 0; --k) {
+                    if ((alive >> k) & 1u) continue;
+                    if (lane == 0)
+                        for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
+                    if constexpr (STORE_E) {
+#pragma unroll
+                        for (int j = 0; j + 1 < KMAX; ++j)
+                            if (j >= k) {
+#pragma unroll
+                                for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
+                            }
+#pragma unroll
+                        for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
+                    }
+                    const uint32_t low = alive & ((1u << k) - 1u);
+                    const uint32_t high = (alive >> (k + 1)) << k;
+                    alive = low | high;
+                    --Kslots;
+                }
+            }
+
+            if (fixed > 0) {
+                if (s == fixed) break;
+                L_prev = L_s;
+                continue;
+            }
+            if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
+            if (s == max_sweeps) {
+                status |= GM_ST_MAXSWEEPS;
+                break;
+            }
+            L_prev = L_s;
+        }
+        if (s > cap_sweeps) s = cap_sweeps;
+
+        // ---------------- penalised state into the output record -------------
+        // (centred coordinates; k_finish turns it into the final mixture)
+        if (tid < K) {
+            const size_t sk = (size_t)c * kmax + tid;
+            const CompState<R, D> cs = compw[0][tid];
+            A.out.omega[sk] = (double)cs.u / (double)G;
+            for (int d = 0; d < D; ++d) A.out.mu[sk * D + d] = (double)cs.mu[d];
+            for (int q = 0; q < NT; ++q) A.out.sigma[sk * NT + q] = (double)cs.S[q];
+        }
+        if (tid == 0) {
+            A.out.K[c] = K;
+            A.out.L_pen[c] = L_s;
+            A.out.sweeps[c] = s;
+            A.out.visits[c] = visits;
+            A.out.status[c] = status;
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
+// k_finish
+// ===========================================================================
+template <int D>
+struct CompF64 {
+    double mu[D];
+    double L[ntri(D)];  // Cholesky factor, packed lower
+    double lnw_c;       // ln w - D/2 ln(2 pi) - ln sqrt det
+};
+
+template <int D>
+__device__ __forceinline__ double ln_term(const CompF64<D>& c, const double (&x)[D])
+{
+    double y[D];
+    if constexpr (D == 1) {
+        y[0] = (x[0] - c.mu[0]) / c.L[0];
+        return c.lnw_c - 0.5 * y[0] * y[0];
+    } else {
+        y[0] = (x[0] - c.mu[0]) / c.L[0];
+        y[1] = (x[1] - c.mu[1] - c.L[1] * y[0]) / c.L[3];
+        y[2] = (x[2] - c.mu[2] - c.L[2] * y[0] - c.L[4] * y[1]) / c.L[5];
+        return c.lnw_c - 0.5 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ bool make_f64(CompF64<D>& c, const double* mu, const double* S, double w)
+{
+    double Sd[ntri(D)], L[ntri(D)];
+#pragma unroll
+    for (int t = 0; t < ntri(D); ++t) Sd[t] = S[t];
+    if (!chol<D, double>(Sd, L)) return false;
+#pragma unroll
+    for (int i = 0; i < D; ++i) c.mu[i] = mu[i];
+#pragma unroll
+    for (int t = 0; t < ntri(D); ++t) c.L[t] = L[t];
+    double lndet = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) lndet += log(L[tri_idx<D>(i, i)]);
+    c.lnw_c = log(w) - 0.5 * D * kLnTwoPi - lndet;
+    return true;
+}
+
+constexpr int kFinishThreads = 256;
+constexpr int kFinishLse = 4096;  // per-particle log-normalisers cached in LDS
+
+template <int D, int KMAX>
+__global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
+{
+    constexpr int NT = ntri(D);
+    constexpr int NS = 1 + D + NT;
+    __shared__ CompF64<D> cf[KMAX];
+    __shared__ double outw[KMAX], outmu[KMAX][D], outS[KMAX][NT];
+    __shared__ double red[2 * kMaxWaves * NS];
+    __shared__ double lse_cache[kFinishLse];
+    __shared__ int s_ok;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x, nthreads = blockDim.x, nwaves = nthreads >> 6;
+    int par = 0;
+    const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+    const int kind = ci->kind;
+    const int kmax = A.kmax;
+    const double T = 0.5 * D * (D + 3);
+    auto clear_slots = [&](int from) {
+        for (int t = from + tid; t < kmax; t += nthreads) {
+            const size_t sk = (size_t)c * kmax + t;
+            A.out.omega[sk] = 0.0;
+            for (int d = 0; d < D; ++d) A.out.mu[sk * D + d] = 0.0;
+            for (int q = 0; q < NT; ++q) A.out.sigma[sk * NT + q] = 0.0;
+        }
+    };
+    if (kind == CELL_INVALID || kind == CELL_EMPTY || kind == CELL_OVERSIZE) {
+        clear_slots(0);
+        if (tid == 0) {
+            A.out.K[c] = 0;
+            A.out.L_pen[c] = 0.0;
+            A.out.L_final[c] = 0.0;
+            A.out.sweeps[c] = 0;
+            A.out.visits[c] = 0;
+            A.out.status[c] = kind == CELL_INVALID ? GM_ST_NONFINITE_INPUT : GM_ST_DEGENERATE;
+        }
+        return;
+    }
+    const int n = ci->n;
+    const int64_t o0 = A.off[c];
+    const double* vc = A.v + o0 * D;
+    const double* ac = A.alpha + o0;
+    const double N = (double)n;
+    const double wscale = N / ci->W;
+    double m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = ci->m[d];
+
+    auto load_x = [&](int i, double (&xv)[D]) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) xv[d] = vc[(size_t)i * D + d] - m[d];
+    };
+    // ln sum_j w_j f_j(x) over cf[0..K-1]
+    auto lse_at = [&](const double (&xv)[D], int K) {
+        double mx = -INFINITY;
+        for (int j = 0; j < K; ++j) mx = fmax(mx, ln_term<D>(cf[j], xv));
+        double se = 0.0;
+        for (int j = 0; j < K; ++j) se += exp(ln_term<D>(cf[j], xv) - mx);
+        return mx + log(se);
+    };
+    auto loglik = [&](int K) {
+        double s[1] = {0.0};
+#pragma unroll 1
+        for (int i = tid; i < n; i += nthreads) {
+            double xv[D];
+            load_x(i, xv);
+            s[0] += ac[i] * wscale * lse_at(xv, K);
+        }
+        block_sum<NS>(s, red, par, nwaves);
+        return s[0];
+    };
+    auto penalty = [&](int K) {
+        double pen = 0.0;
+        for (int j = 0; j < K; ++j) pen += log(outw[j]);
+        const double dpar = K * T + K - 1;
+        return -0.5 * dpar * log(N) - 0.5 * T * pen;
+    };
+
+    int K;
+    int32_t status = 0;
+    double L_pen = 0.0;
+    int sweeps = 0;
+    long long visits = 0;
+    if (kind == CELL_CLOSED) {
+        // a single Gaussian with the cell's own moments (n <= n_min or C singular)
+        K = 1;
+        status = GM_ST_SMALL_CELL_K1;
+        if (tid == 0) {
+            outw[0] = 1.0;
+            for (int d = 0; d < D; ++d) outmu[0][d] = 0.0;
+            for (int q = 0; q < NT; ++q) outS[0][q] = ci->C[q];
+            s_ok = make_f64<D>(cf[0], outmu[0], outS[0], 1.0);
+        }
+        __syncthreads();
+        if (!s_ok) status |= GM_ST_DEGENERATE;
+        const double Lk = s_ok ? loglik(1) + penalty(1) : -INFINITY;
+        L_pen = Lk;
+        if (tid == 0) A.out.L_final[c] = Lk;
+    } else {
+        // unpenalised joint E-step with the penalised parameters, then
+        // eqs. (muk), (sigmak), (omegak-mle)
+        K = A.out.K[c];
+        status = A.out.status[c];
+        L_pen = A.out.L_pen[c];
+        sweeps = A.out.sweeps[c];
+        visits = A.out.visits[c];
+        if (tid < K) {
+            const size_t sk = (size_t)c * kmax + tid;
+            double mu[D], S[NT];
+            for (int d = 0; d < D; ++d) mu[d] = A.out.mu[sk * D + d];
+            for (int q = 0; q < NT; ++q) S[q] = A.out.sigma[sk * NT + q];
+            make_f64<D>(cf[tid], mu, S, A.out.omega[sk]);
+        }
+        __syncthreads();
+        const bool cache = n <= kFinishLse;
+        if (cache) {
+            for (int i = tid; i < n; i += nthreads) {
+                double xv[D];
+                load_x(i, xv);
+                lse_cache[i] = lse_at(xv, K);
+            }
+        }
+        __syncthreads();
+        for (int k = 0; k < K; ++k) {
+            double sm[NS];
+#pragma unroll
+            for (int t = 0; t < NS; ++t) sm[t] = 0.0;
+            const CompF64<D> ck = cf[k];
+#pragma unroll 1
+            for (int i = tid; i < n; i += nthreads) {
+                double xv[D];
+                load_x(i, xv);
+                const double l = cache ? lse_cache[i] : lse_at(xv, K);
+                const double g = ac[i] * wscale * exp(ln_term<D>(ck, xv) - l);
+                double d[D];
+#pragma unroll
+                for (int q = 0; q < D; ++q) d[q] = xv[q] - ck.mu[q];
+                sm[0] += g;
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    const double gd = g * d[q];
+                    sm[1 + q] += gd;
+#pragma unroll
+                    for (int r = q; r < D; ++r) sm[1 + D + tri_idx<D>(q, r)] += gd * d[r];
+                }
+            }
+            block_sum<NS>(sm, red, par, nwaves);
+            if (tid == 0) {
+                const double Nk = sm[0];
+                double dl[D];
+                for (int q = 0; q < D; ++q) {
+                    dl[q] = sm[1 + q] / Nk;
+                    outmu[k][q] = ck.mu[q] + dl[q];
+                }
+                for (int q = 0; q < D; ++q)
+                    for (int r = q; r < D; ++r)
+                        outS[k][tri_idx<D>(q, r)] = sm[1 + D + tri_idx<D>(q, r)] / Nk - dl[q] * dl[r];
+                outw[k] = Nk / N;
+            }
+        }
+        __syncthreads();
+        // the output must factor; otherwise the closed form replaces it
+        if (tid == 0) {
+            bool ok = true;
+            for (int k = 0; k < K; ++k) ok &= make_f64<D>(cf[k], outmu[k], outS[k], outw[k]);
+            if (!ok) {
+                outw[0] = 1.0;
+                for (int d = 0; d < D; ++d) outmu[0][d] = 0.0;
+                for (int q = 0; q < NT; ++q) outS[0][q] = ci->C[q];
+                make_f64<D>(cf[0], outmu[0], outS[0], 1.0);
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!s_ok) {
+            status |= GM_ST_DEGENERATE;
+            K = 1;
+        }
+        const double Lfin = loglik(K) + penalty(K);
+        if (tid == 0) A.out.L_final[c] = Lfin;
+    }
+    // record: mixture in the input coordinates
+    for (int t = tid; t < K; t += nthreads) {
+        const size_t sk = (size_t)c * kmax + t;
+        A.out.omega[sk] = outw[t];
+        for (int d = 0; d < D; ++d) A.out.mu[sk * D + d] = outmu[t][d] + m[d];
+        for (int q = 0; q < NT; ++q) A.out.sigma[sk * NT + q] = outS[t][q];
+    }
+    clear_slots(K);
+    if (tid == 0) {
+        A.out.K[c] = K;
+        A.out.L_pen[c] = L_pen;
+        A.out.sweeps[c] = sweeps;
+        A.out.visits[c] = visits;
+        A.out.status[c] = status;
+    }
+}
+
+// ===========================================================================
+// host-side launch helpers, instantiated per (D, precision) translation unit
+// ===========================================================================
+template <int D, int KMAX, typename R, typename F>
+inline bool with_bucket_kernel(int bucket, F&& f)
+{
+    if constexpr (KMAX == 8) {
+        switch (bucket) {
+            case 0: f(k_em<D, 8, 1, true, R>); return true;
+            case 1: f(k_em<D, 8, 2, true, R>); return true;
+            case 2: f(k_em<D, 8, 4, true, R>); return true;
+            case 3:
+            case 4:
+            case 5:
+            case 6: f(k_em<D, 8, 8, true, R>); return true;
+            case 7: f(k_em<D, 8, 16, false, R>); return true;
+            default: return false;
+        }
+    } else {
+        switch (bucket) {
+            case 0: f(k_em<D, 16, 1, true, R>); return true;
+            case 1: f(k_em<D, 16, 2, true, R>); return true;
+            case 2:
+            case 3:
+            case 4:
+            case 5: f(k_em<D, 16, 4, true, R>); return true;
+            case 6: f(k_em<D, 16, 8, false, R>); return true;
+            case 7: f(k_em<D, 16, 16, false, R>); return true;
+            default: return false;
+        }
+    }
+}
+
+template <int D, typename R>
+int launch_bucket_dr(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+{
+    const dim3 g(grid), b(64 * bucket_cfg(kmax_tpl, bucket).waves);
+    bool ok = false;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, a); };
+    if (kmax_tpl == 8)
+        ok = with_bucket_kernel<D, 8, R>(bucket, go);
+    else if (kmax_tpl == 16)
+        ok = with_bucket_kernel<D, 16, R>(bucket, go);
+    if (!ok) return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int D, typename R>
+int grid_dr(int kmax_tpl, int bucket)
+{
+    static int cache[2][kNumBuckets] = {};
+    const int ki = kmax_tpl == 8 ? 0 : 1;
+    if (cache[ki][bucket] > 0) return cache[ki][bucket];
+    int dev = 0, ncu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const int block = 64 * bucket_cfg(kmax_tpl, bucket).waves;
+    auto q = [&](auto kern) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), block, 0) !=
+            hipSuccess)
+            nb = 1;
+    };
+    if (kmax_tpl == 8)
+        with_bucket_kernel<D, 8, R>(bucket, q);
+    else
+        with_bucket_kernel<D, 16, R>(bucket, q);
+    if (nb < 1) nb = 1;
+    cache[ki][bucket] = nb * ncu;
+    return cache[ki][bucket];
+}
+
+// pre- and post-EM kernels of one D
+template <int D>
+int launch_pre_dr(const CompressArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan_reset, dim3(1), dim3(64), 0, st, a.plan);
+    hipLaunchKernelGGL(k_moments<D>, dim3((unsigned)a.n_cells), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1), 0, st, a.plan);
+    hipLaunchKernelGGL(k_plan_scatter<D>, dim3((unsigned)((a.n_cells + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int D>
+int launch_finish_dr(int kmax_tpl, const CompressArgs& a, hipStream_t st)
+{
+    if (kmax_tpl == 8)
+        hipLaunchKernelGGL((k_finish<D, 8>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_finish<D, 16>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace gm

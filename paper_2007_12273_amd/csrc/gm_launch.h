@@ -1,0 +1,62 @@
+// gm_launch.h -- internal launch interface between the C ABI layer and the
+// kernel translation units of libgmcr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gmcr.h"
+
+namespace gm {
+
+// ---- compress ------------------------------------------------------------
+struct CompressArgs;
+
+// Length buckets: cell n -> first bucket with n <= max_n (64 * 2^b).  Each
+// bucket is run by one persistent launch of 64 * waves threads per
+// workgroup, each thread holding `per_thread` particles.  `store_e` buckets
+// keep every density term in registers, so the particles per thread depend
+// on the number of component slots (KMAX): the register file holds
+// (KMAX + D + 2) values per particle.
+struct Bucket {
+    int max_n;
+    int per_thread;
+    int waves;
+    bool store_e;
+};
+constexpr int kNumBuckets = 8;
+constexpr Bucket kBuckets8[kNumBuckets] = {
+    {64, 1, 1, true},   {128, 2, 1, true},  {256, 4, 1, true},  {512, 8, 1, true},
+    {1024, 8, 2, true}, {2048, 8, 4, true}, {4096, 8, 8, true}, {8192, 16, 8, false},
+};
+constexpr Bucket kBuckets16[kNumBuckets] = {
+    {64, 1, 1, true},   {128, 2, 1, true},  {256, 4, 1, true},  {512, 4, 2, true},
+    {1024, 4, 4, true}, {2048, 4, 8, true}, {4096, 8, 8, false}, {8192, 16, 8, false},
+};
+__host__ __device__ constexpr const Bucket& bucket_cfg(int kmax_tpl, int b)
+{
+    return kmax_tpl == 8 ? kBuckets8[b] : kBuckets16[b];
+}
+constexpr int kMaxCellParticles = 8192;
+constexpr int kEmMaxThreads = 512;
+
+// ---- reconstruct ---------------------------------------------------------
+struct ReconArgs {
+    const int32_t* K;
+    const double* omega;
+    const double* mu;
+    const double* sigma;
+    int32_t kmax;
+    const int64_t* out_off;
+    const double* target;
+    int32_t D, dx;
+    uint64_t seed;
+    double* v_out;
+    double* w_out;
+    double* x_out;
+    int32_t* status;
+};
+
+int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st);
+
+}  // namespace gm

@@ -1,0 +1,222 @@
+// gm_reconstruct.hip -- per-cell ancestral sampling of a Gaussian mixture
+// (Sec. 2.4, eq. mix-dist-1) followed by Lemons' moment-matching projection
+// (Sec. 2.4.2, eqs. alpha/beta), FP64 throughout.
+//
+// One workgroup per cell.  Every particle is generated once from its own
+// Philox counter; up to RP particles per thread stay in registers between
+// the sample-moment reduction and the projected write, so the output is
+// written exactly once.  Cells larger than RP * blockDim regenerate their
+// particles in a second pass instead of re-reading them.
+#include "gm_device.h"
+#include "gm_launch.h"
+
+namespace gm {
+
+constexpr int kReconThreads = 256;
+constexpr int kReconRegs = 8;
+
+// Particle i of cell c: uniform j is word j % 4 of Philox block j / 4 with
+// counter (i, c, j / 4, 0) and key (seed, "RECO").  Uniform 0 picks the
+// component, the next ceil(D/2) pairs feed Box-Muller, the rest are positions.
+template <int D>
+__device__ __forceinline__ void draw_particle(uint64_t seed, int c, int64_t i, int K, const double* cum,
+                                              const double (*mu)[D], const double (*L)[ntri(D)], int dx,
+                                              double (&v)[D], double (&xpos)[3])
+{
+    constexpr int NPAIR = (D + 1) / 2;
+    const u64x4 b0 = philox4x64_10((uint64_t)i, (uint64_t)c, 0, 0, seed, kTagRecon);
+    double u[8];
+    u[0] = unit53(b0.x);
+    u[1] = unit53(b0.y);
+    u[2] = unit53(b0.z);
+    u[3] = unit53(b0.w);
+    const int nu = 1 + 2 * NPAIR + dx;
+    if (nu > 4) {
+        const u64x4 b1 = philox4x64_10((uint64_t)i, (uint64_t)c, 1, 0, seed, kTagRecon);
+        u[4] = unit53(b1.x);
+        u[5] = unit53(b1.y);
+        u[6] = unit53(b1.z);
+        u[7] = unit53(b1.w);
+    }
+    // component by inverse CDF over the cumulative weights
+    int k = 0;
+    while (k < K - 1 && !(u[0] < cum[k])) ++k;
+    // Box-Muller pairs
+    double z[2 * NPAIR];
+#pragma unroll
+    for (int pr = 0; pr < NPAIR; ++pr) {
+        const double r = sqrt(-2.0 * log(1.0 - u[1 + 2 * pr]));
+        const double th = 6.283185307179586476925286766559 * u[2 + 2 * pr];
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        z[2 * pr] = r * cs;
+        z[2 * pr + 1] = r * sn;
+    }
+    // v = mu_k + L_k z   (L packed lower, row-major)
+    if constexpr (D == 1) {
+        v[0] = mu[k][0] + L[k][0] * z[0];
+    } else {
+        v[0] = mu[k][0] + L[k][0] * z[0];
+        v[1] = mu[k][1] + (L[k][1] * z[0] + L[k][3] * z[1]);
+        v[2] = mu[k][2] + (L[k][2] * z[0] + L[k][4] * z[1] + L[k][5] * z[2]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xpos[d] = (d < dx) ? u[1 + 2 * NPAIR + d] : 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
+{
+    constexpr int NT = ntri(D);
+    constexpr int KM = 16;
+    __shared__ double s_mu[KM][D], s_L[KM][NT], s_cum[KM];
+    __shared__ double red[2 * kMaxWaves * (2 + D)];
+    __shared__ int s_bad;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    const int nwaves = nthreads >> 6;
+    int par = 0;
+    const int64_t o0 = A.out_off[c];
+    const int64_t n = A.out_off[c + 1] - o0;
+    const int kmax = A.kmax;
+    const int K = A.K[c];
+    const int dx = A.dx;
+    if (n <= 0) {
+        if (tid == 0) A.status[c] = 0;
+        return;
+    }
+    if (K < 1 || K > kmax) {
+        for (int64_t i = tid; i < n; i += nthreads) {
+            for (int d = 0; d < D; ++d) A.v_out[(o0 + i) * D + d] = 0.0;
+            A.w_out[o0 + i] = 0.0;
+            for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = 0.0;
+        }
+        if (tid == 0) A.status[c] = GM_ST_DEGENERATE;
+        return;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    if (tid < K) {
+        const size_t s = (size_t)c * kmax + tid;
+        double S[NT], L[NT];
+        for (int q = 0; q < NT; ++q) S[q] = A.sigma[s * NT + q];
+        if (!chol<D, double>(S, L)) {
+            for (int q = 0; q < NT; ++q) L[q] = 0.0;  // sample the mean only
+            s_bad = 1;
+        }
+        for (int q = 0; q < NT; ++q) s_L[tid][q] = L[q];
+        for (int d = 0; d < D; ++d) s_mu[tid][d] = A.mu[s * D + d];
+    }
+    if (tid == 0) {
+        double run = 0.0;
+        for (int k = 0; k < K; ++k) {
+            run += A.omega[(size_t)c * kmax + k];
+            s_cum[k] = run;
+        }
+        s_cum[K - 1] = 1.0;
+    }
+    __syncthreads();
+    // targets from the compress moments record: W, P = sum alpha v, and
+    // E = tr(S) / 2 with S = sum alpha v v^T
+    const double* tg = A.target + (size_t)c * nmom(D);
+    const double W = tg[0];
+    const double wp = W / (double)n;
+    const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
+
+    double vr[kReconRegs][D];
+    double acc[2 + D];
+#pragma unroll
+    for (int t = 0; t < 2 + D; ++t) acc[t] = 0.0;
+    auto add_moments = [&](const double (&v)[D]) {
+        acc[0] += wp;
+        double e = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            acc[1 + d] += wp * v[d];
+            e += 0.5 * wp * v[d] * v[d];
+        }
+        acc[1 + D] += e;
+    };
+    // pass 1: draw, write weights and positions, reduce N', p', E'
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kReconRegs; ++j) {
+            const int64_t i = tid + (int64_t)j * nthreads;
+            if (i < n) {
+                double xp[3];
+                draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, vr[j], xp);
+                A.w_out[o0 + i] = wp;
+                for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
+                add_moments(vr[j]);
+            }
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += nthreads) {
+            double v[D], xp[3];
+            draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, v, xp);
+            A.w_out[o0 + i] = wp;
+            for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
+            add_moments(v);
+        }
+    }
+    block_sum<2 + D>(acc, red, par, nwaves);
+    // Lemons: a = sqrt((2 E N' - |P|^2) / (2 E' N' - |p'|^2)), beta = (P - a p') / (a N')
+    double E = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) E += tg[1 + D + tri_idx<D>(d, d)];
+    E *= 0.5;
+    const double Np = acc[0], Ep = acc[1 + D];
+    double P2 = 0.0, pp2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        P2 += tg[1 + d] * tg[1 + d];
+        pp2 += acc[1 + d] * acc[1 + d];
+    }
+    // each bracket is a difference of terms of size 2 E N'; within rounding
+    // of zero (1e-12 of the term) it counts as zero -- the denominator
+    // vanishes exactly when every drawn velocity is the same (n' = 1)
+    const double num = 2.0 * E * Np - P2;
+    const double den = 2.0 * Ep * Np - pp2;
+    const bool project = num > 1e-12 * (2.0 * E * Np) && den > 1e-12 * (2.0 * Ep * Np);
+    double sc = 1.0, beta[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) beta[d] = 0.0;
+    if (project) {
+        sc = sqrt(num / den);
+#pragma unroll
+        for (int d = 0; d < D; ++d) beta[d] = (tg[1 + d] - sc * acc[1 + d]) / (sc * Np);
+    }
+    auto write_v = [&](int64_t i, const double (&v)[D]) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) A.v_out[(o0 + i) * D + d] = project ? sc * (v[d] + beta[d]) : v[d];
+    };
+    // pass 2: projected velocities
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kReconRegs; ++j) {
+            const int64_t i = tid + (int64_t)j * nthreads;
+            if (i < n) write_v(i, vr[j]);
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += nthreads) {
+            double v[D], xp[3];
+            draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, 0, v, xp);
+            write_v(i, v);
+        }
+    }
+    if (tid == 0) A.status[c] = (project ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
+}
+
+int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st)
+{
+    if (n_cells == 0) return 0;
+    const dim3 grid((unsigned)n_cells), block(kReconThreads);
+    if (a.D == 1)
+        hipLaunchKernelGGL(k_reconstruct<1>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_reconstruct<3>, grid, block, 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace gm

@@ -1,0 +1,64 @@
+"""The C-ABI library builds, loads and exports every entry point that
+include/gmcr.h declares (no GPU needed: nothing is called that computes)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(gm_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("gm_compress", "gm_reconstruct", "gm_compress_workspace", "gm_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for n in sorted(declared()):
+        assert hasattr(L, n), n
+    # host-only helpers that touch no device
+    lib = _lib.load()
+    assert lib.gm_version() >= 100
+    assert lib.gm_strerror(0) == b"success"
+    o = _lib.GmOpts()
+    lib.gm_opts_default(ctypes.byref(o), 3, 16)
+    assert (o.D, o.kmax, o.n_min, o.max_sweeps, o.tol_rel) == (3, 16, 10, 1000, 1e-7)
+    assert lib.gm_compress_workspace(4096, ctypes.byref(o)) > 4096 * 4
+
+
+def test_invalid_arguments_rejected_on_host():
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    o = _lib.GmOpts()
+    lib.gm_opts_default(ctypes.byref(o), 2, 8)  # D = 2 is not built
+    m = _lib.GmMix()
+    assert lib.gm_compress(None, None, None, 1, ctypes.byref(o), None, None, ctypes.byref(m), None, 0, None) == -1
+    lib.gm_opts_default(ctypes.byref(o), 3, 17)  # kmax above 16
+    assert lib.gm_compress(None, None, None, 1, ctypes.byref(o), None, None, ctypes.byref(m), None, 0, None) == -1
+    lib.gm_opts_default(ctypes.byref(o), 3, 8)
+    o.n_min = 3  # below floor(T/2) = 4 in 3V
+    assert lib.gm_compress(None, None, None, 1, ctypes.byref(o), None, None, ctypes.byref(m), None, 0, None) == -1
+    # zero cells is a no-op
+    lib.gm_opts_default(ctypes.byref(o), 3, 8)
+    assert lib.gm_compress(None, None, None, 0, ctypes.byref(o), None, None, ctypes.byref(m), None, 0, None) == 0
+    # reconstruct: bad dx
+    assert lib.gm_reconstruct(None, None, None, None, 8, None, None, 1, 3, 4, 0, None, None, None, None, None, 0,
+                              None) == -1

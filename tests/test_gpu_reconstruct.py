@@ -1,0 +1,75 @@
+"""GPU reconstruct (gm_reconstruct through the C ABI) against the FP64 oracle
+on the same mixtures: every particle to 1e-12 (the same Philox streams,
+categorical draws and Box-Muller normals), statuses exactly, and the
+projected sample's W, P, E equal to the targets to 1e-12."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12273_amd import synth
+
+from gpu_util import dev, host, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_recon(mix, moments, out_off, D, dx, seed):
+    from paper_2007_12273_amd import api
+    g = dev()
+    t = lambda x, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(x)).to(g).to(dt)
+    r = api.reconstruct(t(mix["K"], torch.int32), t(mix["omega"]), t(mix["mu"]), t(mix["sigma"]),
+                        t(out_off, torch.int64), t(moments), D, dx, seed)
+    torch.cuda.synchronize()
+    return host(r)
+
+
+@pytest.mark.parametrize("name,nc,dx,factor", [("weibel_3v", 40, 1, 1.0), ("grid_3v", 300, 2, 1.0),
+                                               ("mix_1v", 40, 1, 0.5), ("weibel_3v", 12, 3, 3.0)])
+def test_reconstruct_matches_oracle(name, nc, dx, factor):
+    d = synth.make(name) if name != "grid_3v" else synth.make(name, n_cells=1024)
+    off = d["cell_off"]
+    D, kmax = d["D"], d["kmax"]
+    sub = dict(v=d["v"][:off[nc]], alpha=d["alpha"][:off[nc]], cell_off=off[:nc + 1])
+    mix = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=kmax, seed=1, max_sweeps=25)
+    counts = np.maximum(0, np.round(np.diff(sub["cell_off"]) * factor)).astype(np.int64)
+    counts[0] = 1  # a cell where the projection has no solution
+    out_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    tg = oracle.targets_from_moments(mix["moments"], D)
+    o = oracle.reconstruct(mix["K"], mix["omega"], mix["mu"], mix["sigma"], out_off, tg, D, dx, seed=3003)
+    g = _gpu_recon(mix, mix["moments"], out_off, D, dx, 3003)
+    assert np.array_equal(g["status"], o["status"])
+    assert o["status"][0] == oracle.STATUS["LEMONS_SKIPPED"]
+    np.testing.assert_allclose(g["w"], o["w"], rtol=1e-15, atol=0)
+    if dx:
+        assert np.array_equal(g["x"], o["x"])  # positions are raw uniforms
+    scale = np.sqrt(np.maximum(tg[:, 1 + D] / tg[:, 0], 1e-300))  # thermal-plus-drift speed per cell
+    cell_of = np.repeat(np.arange(nc), counts)
+    err = np.abs(g["v"] - o["v"]).max(axis=1) / scale[cell_of]
+    assert err.max() < 1e-12, err.max()
+    # conservation of the projected sample
+    for c in range(1, nc):
+        sl = slice(out_off[c], out_off[c + 1])
+        if sl.stop == sl.start:
+            continue
+        w, v = g["w"][sl], g["v"][sl]
+        assert abs(w.sum() - tg[c, 0]) <= 1e-13 * tg[c, 0]
+        P = (w[:, None] * v).sum(0)
+        E = 0.5 * (w * (v * v).sum(1)).sum()
+        assert np.abs(P - tg[c, 1:1 + D]).max() <= 1e-12 * np.sqrt(2 * tg[c, 0] * tg[c, 1 + D])
+        assert abs(E - tg[c, 1 + D]) <= 1e-12 * tg[c, 1 + D]
+
+
+def test_reconstruct_large_cell_regenerates():
+    """A cell above the register-resident size takes the two-pass path."""
+    D = 3
+    K = np.array([2], np.int32)
+    w = np.array([[0.7, 0.3]])
+    mu = np.array([[[0.1, 0.0, 0.0], [-0.2, 0.1, 0.0]]])
+    S = np.array([[[0.01, 0.001, 0, 0.02, 0, 0.015], [0.004, 0, 0, 0.004, 0, 0.004]]])
+    mom = np.array([[2.0, 0.05, 0.02, 0.0, 0.05, 0.0, 0.0, 0.04, 0.0, 0.035]])
+    out_off = np.array([0, 5000], np.int64)
+    tg = oracle.targets_from_moments(mom, D)
+    o = oracle.reconstruct(K, w, mu, S, out_off, tg, D, 1, seed=9)
+    g = _gpu_recon({"K": K, "omega": w, "mu": mu, "sigma": S}, mom, out_off, D, 1, 9)
+    assert np.array_equal(g["status"], o["status"])
+    assert np.abs(g["v"] - o["v"]).max() < 1e-12 * np.sqrt(tg[0, 1 + D] / tg[0, 0])
