@@ -281,15 +281,34 @@ static void unpack_sym(int D, const double* in, double S[ORC_MAXD][ORC_MAXD])
         }
 }
 
-/* One E-step for component k (eq. responsibility):
- *   gamma_pk = a_p w_k f_k(v_p) / sum_j w_j f_j(v_p)
- * using the current parameters of all live components. */
-static void responsibilities(int D, const mixture* m, int k, int n, const double* x, const double* a, double* g)
+/* gamma_pj = a_p w_j f_j(v_p) / sum_i w_i f_i(v_p) for all j (eq.
+ * responsibility), formed as a ratio of the same exponentials (scaled by the
+ * largest term) so that sum_j gamma_pj = a_p (eq. Sum_responsibility) holds to
+ * rounding whatever the size of the log-densities. */
+static void particle_responsibilities(int D, const mixture* m, const double* x, double a, double* g)
 {
     double ell[ORC_MAXK];
+    double mx = -INFINITY;
+    for (int j = 0; j < m->K; ++j) {
+        ell[j] = log(m->w[j]) + log_normal(D, x, m->mu[j], m->L[j]);
+        if (ell[j] > mx) mx = ell[j];
+    }
+    double s = 0.0;
+    for (int j = 0; j < m->K; ++j) {
+        g[j] = exp(ell[j] - mx);
+        s += g[j];
+    }
+    for (int j = 0; j < m->K; ++j) g[j] = a * g[j] / s;
+}
+
+/* One E-step for component k with the current parameters of all live
+ * components. */
+static void responsibilities(int D, const mixture* m, int k, int n, const double* x, const double* a, double* g)
+{
+    double gp[ORC_MAXK];
     for (int p = 0; p < n; ++p) {
-        double lse = mixture_lse(D, m, x + (size_t)p * D, ell);
-        g[p] = a[p] * exp(ell[k] - lse);
+        particle_responsibilities(D, m, x + (size_t)p * D, a[p], gp);
+        g[p] = gp[k];
     }
 }
 
@@ -316,12 +335,12 @@ static void mean_cov(int D, int n, const double* x, const double* g, double Nk, 
  * Returns 0, or -1 if a resulting covariance is not positive definite. */
 static int mle_finish(int D, mixture* m, int n, const double* x, const double* a, double N, double* g_all)
 {
-    double ell[ORC_MAXK];
+    double gp[ORC_MAXK];
     int K = m->K;
     /* joint E-step: every gamma_p. comes from the same parameters */
     for (int p = 0; p < n; ++p) {
-        double lse = mixture_lse(D, m, x + (size_t)p * D, ell);
-        for (int k = 0; k < K; ++k) g_all[(size_t)k * n + p] = a[p] * exp(ell[k] - lse);
+        particle_responsibilities(D, m, x + (size_t)p * D, a[p], gp);
+        for (int k = 0; k < K; ++k) g_all[(size_t)k * n + p] = gp[k];
     }
     mixture out = *m;
     for (int k = 0; k < K; ++k) {
@@ -508,10 +527,10 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
              * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
             double* gk = g;
             mixture next = m;
-            double ell[ORC_MAXK];
+            double gp[ORC_MAXK];
             for (int p = 0; p < n; ++p) {
-                double lse = mixture_lse(D, &m, x + (size_t)p * D, ell);
-                for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = a[p] * exp(ell[k] - lse);
+                particle_responsibilities(D, &m, x + (size_t)p * D, a[p], gp);
+                for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = gp[k];
             }
             for (int k = 0; k < m.K; ++k) {
                 double Nk = 0.0;

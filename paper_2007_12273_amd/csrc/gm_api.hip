@@ -50,8 +50,14 @@ struct WsLayout {
 
 // auxiliary streams for concurrent length buckets, one set per device
 constexpr int kLanes = 4;
-// bucket -> lane (0..2 auxiliary, 3 the caller's stream), largest first per lane
-constexpr int kBucketLane[gm::kNumBuckets] = {2, 1, 0, 3, 3, 2, 1, 0};
+// bucket -> lane (0..2 auxiliary, 3 the caller's stream).  Each bucket's
+// makespan is set by its slowest cell, so the mapping spreads the buckets
+// that measured longest on the 1D3V Weibel-like workload over different
+// lanes (the 257-512 bucket holds small cells that keep 16 components for
+// the whole sweep cap; the two recompute-mode buckets hold the largest
+// cells); buckets are launched largest first on every lane.
+constexpr int kBucketLane16[gm::kNumBuckets] = {0, 0, 0, 0, 3, 3, 1, 2, 3, 3, 1, 2};
+constexpr int kBucketLane8[gm::kNumBuckets] = {0, 1, 2, 3, 0, 1, 2, 3, 0, 1, 2, 3};
 struct Fork {
     hipStream_t aux[kLanes - 1];
     hipEvent_t fork;
@@ -177,7 +183,7 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
     for (int i = 0; i < kLanes - 1; ++i)
         if (hipStreamWaitEvent(fk->aux[i], fk->fork, 0) != hipSuccess) return GM_EHIP;
     for (int b = gm::kNumBuckets - 1; b >= 0; --b) {
-        hipStream_t bs = lanes[kBucketLane[b]];
+        hipStream_t bs = lanes[kt == 8 ? kBucketLane8[b] : kBucketLane16[b]];
         int grid = 0;
         if (D == 1)
             grid = fp64 ? gm::grid_compress_d1_double(kt, b) : gm::grid_compress_d1_float(kt, b);

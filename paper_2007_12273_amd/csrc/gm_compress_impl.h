@@ -82,10 +82,10 @@ constexpr double kLog2TwoPi = 2.6514961294723187980;
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLnTwoPi = 1.8378770664093454836;
 
-__host__ __device__ inline int bucket_of(int n)
+__host__ __device__ inline int bucket_of(int kmax_tpl, int n)
 {
     for (int b = 0; b < kNumBuckets; ++b)
-        if (n <= kBuckets8[b].max_n) return b;
+        if (n <= bucket_cfg(kmax_tpl, b).max_n) return b;
     return -1;
 }
 
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
         const bool closed = n <= A.n_min || !spd;
         ci->kind = closed ? CELL_CLOSED : CELL_EM;
         if (!closed) {
-            atomicAdd(&A.plan[PLAN_COUNT + bucket_of(n)], 1);
+            atomicAdd(&A.plan[PLAN_COUNT + bucket_of(A.kmax <= 8 ? 8 : 16, n)], 1);
             // cold start: min(kmax, n, floor(N/T)) distinct particles by a
             // partial Fisher-Yates draw; draw j swaps positions j and
             // j + floor(x (n - j) / 2^64), x the first word of Philox with key
@@ -240,7 +240,7 @@ __global__ void k_plan_scatter(CompressArgs A)
     if (c >= A.n_cells) return;
     const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
     if (ci->kind != CELL_EM) return;
-    const int b = bucket_of(ci->n);
+    const int b = bucket_of(A.kmax <= 8 ? 8 : 16, ci->n);
     const int pos = atomicAdd(&A.plan[PLAN_CURSOR + b], 1);
     A.list[A.plan[PLAN_BASE + b] + pos] = (int32_t)c;
 }
@@ -587,8 +587,9 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                 }
                 block_sum<NS>(sums, red_r, par_r, nwaves);
                 const R Nk = sums[0];
-                if (fabs((double)Nk - halfT) < 1e-5 * halfT) status |= GM_ST_NEAR_TIE;
-                if ((double)Nk - halfT <= 0.0) {
+                const R NkT = Nk - (R)halfT;
+                if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
+                if (NkT <= R(0)) {
                     // annihilate k (eq. omegak); the weights renormalise through G
                     alive &= ~(1u << k);
                     G -= cku;
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
 #pragma unroll
                     for (int j = i; j < D; ++j)
                         cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
-                const R wk = (R)(((double)Nk - halfT) / (N - halfT * K));
+                const R wk = NkT * m_rcp((R)(N - halfT * K));
                 const R unew = wk * G;
                 G = G - cku + unew;
                 cn.u = unew;
@@ -775,8 +776,10 @@ struct CompF64 {
     double lnw_c;       // ln w - D/2 ln(2 pi) - ln sqrt det
 };
 
+// not inlined: the normaliser pass and the component passes must evaluate
+// each term with the same instruction sequence
 template <int D>
-__device__ __forceinline__ double ln_term(const CompF64<D>& c, const double (&x)[D])
+__device__ __noinline__ double ln_term(const CompF64<D>& c, const double (&x)[D])
 {
     double y[D];
     if constexpr (D == 1) {
@@ -809,7 +812,7 @@ __device__ __forceinline__ bool make_f64(CompF64<D>& c, const double* mu, const 
 }
 
 constexpr int kFinishThreads = 256;
-constexpr int kFinishLse = 4096;  // per-particle log-normalisers cached in LDS
+constexpr int kFinishCache = 2048;  // per-particle normalisers cached in LDS
 
 template <int D, int KMAX>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
@@ -819,7 +822,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
     __shared__ CompF64<D> cf[KMAX];
     __shared__ double outw[KMAX], outmu[KMAX][D], outS[KMAX][NT];
     __shared__ double red[2 * kMaxWaves * NS];
-    __shared__ double lse_cache[kFinishLse];
+    __shared__ double mx_cache[kFinishCache], sum_cache[kFinishCache];
     __shared__ int s_ok;
     const int c = blockIdx.x;
     const int tid = threadIdx.x, nthreads = blockDim.x, nwaves = nthreads >> 6;
@@ -862,12 +865,16 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
 #pragma unroll
         for (int d = 0; d < D; ++d) xv[d] = vc[(size_t)i * D + d] - m[d];
     };
-    // ln sum_j w_j f_j(x) over cf[0..K-1]
-    auto lse_at = [&](const double (&xv)[D], int K) {
-        double mx = -INFINITY;
+    // largest log term and the sum of exp(term - largest) over cf[0..K-1]
+    auto norm_at = [&](const double (&xv)[D], int K, double& mx, double& se) {
+        mx = -INFINITY;
         for (int j = 0; j < K; ++j) mx = fmax(mx, ln_term<D>(cf[j], xv));
-        double se = 0.0;
+        se = 0.0;
         for (int j = 0; j < K; ++j) se += exp(ln_term<D>(cf[j], xv) - mx);
+    };
+    auto lse_at = [&](const double (&xv)[D], int K) {
+        double mx, se;
+        norm_at(xv, K, mx, se);
         return mx + log(se);
     };
     auto loglik = [&](int K) {
@@ -924,12 +931,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             make_f64<D>(cf[tid], mu, S, A.out.omega[sk]);
         }
         __syncthreads();
-        const bool cache = n <= kFinishLse;
+        // gamma_pk = a_p exp(l_k - mx_p) / sum_j exp(l_j - mx_p): a ratio of
+        // the same exponentials, so sum_k gamma_pk = a_p to rounding
+        const bool cache = n <= kFinishCache;
         if (cache) {
             for (int i = tid; i < n; i += nthreads) {
                 double xv[D];
                 load_x(i, xv);
-                lse_cache[i] = lse_at(xv, K);
+                norm_at(xv, K, mx_cache[i], sum_cache[i]);
             }
         }
         __syncthreads();
@@ -942,8 +951,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             for (int i = tid; i < n; i += nthreads) {
                 double xv[D];
                 load_x(i, xv);
-                const double l = cache ? lse_cache[i] : lse_at(xv, K);
-                const double g = ac[i] * wscale * exp(ln_term<D>(ck, xv) - l);
+                double mx, se;
+                if (cache) {
+                    mx = mx_cache[i];
+                    se = sum_cache[i];
+                } else {
+                    norm_at(xv, K, mx, se);
+                }
+                const double g = ac[i] * wscale * exp(ln_term<D>(ck, xv) - mx) / se;
                 double d[D];
 #pragma unroll
                 for (int q = 0; q < D; ++q) d[q] = xv[q] - ck.mu[q];
@@ -1014,30 +1029,23 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
 template <int D, int KMAX, typename R, typename F>
 inline bool with_bucket_kernel(int bucket, F&& f)
 {
-    if constexpr (KMAX == 8) {
-        switch (bucket) {
-            case 0: f(k_em<D, 8, 1, true, R>); return true;
-            case 1: f(k_em<D, 8, 2, true, R>); return true;
-            case 2: f(k_em<D, 8, 4, true, R>); return true;
-            case 3:
-            case 4:
-            case 5:
-            case 6: f(k_em<D, 8, 8, true, R>); return true;
-            case 7: f(k_em<D, 8, 16, false, R>); return true;
-            default: return false;
-        }
-    } else {
-        switch (bucket) {
-            case 0: f(k_em<D, 16, 1, true, R>); return true;
-            case 1: f(k_em<D, 16, 2, true, R>); return true;
-            case 2:
-            case 3:
-            case 4:
-            case 5: f(k_em<D, 16, 4, true, R>); return true;
-            case 6: f(k_em<D, 16, 8, false, R>); return true;
-            case 7: f(k_em<D, 16, 16, false, R>); return true;
-            default: return false;
-        }
+    if (bucket < 0 || bucket >= kNumBuckets) return false;
+    const Bucket& b = bucket_cfg(KMAX, bucket);
+    if (!b.store_e) {
+        if (b.per_thread == 8) f(k_em<D, KMAX, 8, false, R>);
+        else f(k_em<D, KMAX, 16, false, R>);
+        return true;
+    }
+    switch (b.per_thread) {
+        case 1: f(k_em<D, KMAX, 1, true, R>); return true;
+        case 2: f(k_em<D, KMAX, 2, true, R>); return true;
+        case 4: f(k_em<D, KMAX, 4, true, R>); return true;
+        default:
+            if constexpr (KMAX == 8) {
+                f(k_em<D, KMAX, 8, true, R>);
+                return true;
+            }
+            return false;
     }
 }
 

@@ -24,14 +24,20 @@ struct Bucket {
     int waves;
     bool store_e;
 };
-constexpr int kNumBuckets = 8;
+constexpr int kNumBuckets = 12;
+// KMAX = 8: 8 register-resident particles per thread up to 8 waves (4096
+// particles), then the recompute mode.
 constexpr Bucket kBuckets8[kNumBuckets] = {
-    {64, 1, 1, true},   {128, 2, 1, true},  {256, 4, 1, true},  {512, 8, 1, true},
-    {1024, 8, 2, true}, {2048, 8, 4, true}, {4096, 8, 8, true}, {8192, 16, 8, false},
+    {64, 1, 1, true},    {128, 2, 1, true},   {256, 4, 1, true},    {512, 8, 1, true},
+    {1024, 8, 2, true},  {1536, 8, 3, true},  {2048, 8, 4, true},   {2560, 8, 5, true},
+    {3072, 8, 6, true},  {3584, 8, 7, true},  {4096, 8, 8, true},   {8192, 16, 8, false},
 };
+// KMAX = 16: 4 register-resident particles per thread, one bucket per wave
+// count up to 8 waves (2048 particles), then the recompute mode.
 constexpr Bucket kBuckets16[kNumBuckets] = {
-    {64, 1, 1, true},   {128, 2, 1, true},  {256, 4, 1, true},  {512, 4, 2, true},
-    {1024, 4, 4, true}, {2048, 4, 8, true}, {4096, 8, 8, false}, {8192, 16, 8, false},
+    {64, 1, 1, true},    {128, 2, 1, true},   {256, 4, 1, true},    {512, 4, 2, true},
+    {768, 4, 3, true},   {1024, 4, 4, true},  {1280, 4, 5, true},   {1536, 4, 6, true},
+    {1792, 4, 7, true},  {2048, 4, 8, true},  {4096, 8, 8, false},  {8192, 16, 8, false},
 };
 __host__ __device__ constexpr const Bucket& bucket_cfg(int kmax_tpl, int b)
 {
