@@ -79,7 +79,7 @@ def _declare(L):
 
 
 def _declare_mlp(L):
-    L.orc_features.argtypes = [P, P, P, I64, P, ctypes.c_int]
+    L.orc_features.argtypes = [P, P, P, I64, P, P]
     L.orc_features.restype = ctypes.c_int
     L.orc_mlp_forward.argtypes = [P, ctypes.c_int, P, P, P, P, P, P, ctypes.c_int, P, P, P]
     L.orc_mlp_forward.restype = ctypes.c_int
@@ -227,3 +227,69 @@ def targets_from_moments(moments, D):
     diag = [1 + D + i * D - i * (i - 1) // 2 for i in range(D)]
     E = 0.5 * sum(mom[:, j] for j in diag)
     return np.concatenate([W[:, None], P, E[:, None]], axis=1)
+
+
+# ---------------------------------------------------------------- warm start
+NF, NH, NO = 105, 256, 160
+
+
+def features(v, alpha, cell_off):
+    """105 features and the whitening frame (m, L_C packed lower) per 3V cell."""
+    v = _c(v, np.float64)
+    off = _c(cell_off, np.int64)
+    n_cells = len(off) - 1
+    f = np.zeros((n_cells, NF))
+    fr = np.zeros((n_cells, 9))
+    lib().orc_features(_p(v), _p(_c(alpha, np.float64)), _p(off), n_cells, _p(f), _p(fr))
+    return f, fr
+
+
+def mlp_forward(X, params, bf16=False):
+    X = _c(X, np.float64)
+    B = X.shape[0]
+    W1, b1, W2, b2, W3, b3 = [_c(params[k], np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    H1 = np.zeros((B, NH))
+    H2 = np.zeros((B, NH))
+    Y = np.zeros((B, NO))
+    lib().orc_mlp_forward(_p(X), B, _p(W1), _p(b1), _p(W2), _p(b2), _p(W3), _p(b3), int(bf16), _p(H1), _p(H2),
+                          _p(Y))
+    return H1, H2, Y
+
+
+def mlp_loss_backward(X, params, targets, lam=1.0, bf16=False):
+    """Loss (mean over rows) and gradients {W1, b1, ..., b3, dY}."""
+    X = _c(X, np.float64)
+    B = X.shape[0]
+    Wn = [_c(params[k], np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    g = {k: np.zeros_like(w) for k, w in zip(("W1", "b1", "W2", "b2", "W3", "b3"), Wn)}
+    g["dY"] = np.zeros((B, NO))
+    Tg = _c(targets, np.float64)
+    L = lib().orc_mlp_loss_backward(_p(X), B, *[_p(w) for w in Wn], _p(Tg), float(lam), int(bf16),
+                                    _p(g["W1"]), _p(g["b1"]), _p(g["W2"]), _p(g["b2"]), _p(g["W3"]), _p(g["b3"]),
+                                    _p(g["dY"]))
+    return L, g
+
+
+def warm_decode(Y, frame, cell_off, kmax):
+    Y = _c(Y, np.float64)
+    fr = _c(frame, np.float64)
+    off = _c(cell_off, np.int64)
+    n_cells = len(off) - 1
+    K = np.zeros(n_cells, np.int32)
+    w = np.zeros((n_cells, kmax))
+    mu = np.zeros((n_cells, kmax, 3))
+    S = np.zeros((n_cells, kmax, 6))
+    lib().orc_warm_decode(_p(Y), _p(fr), _p(off), n_cells, kmax, _p(K), _p(w), _p(mu), _p(S))
+    return {"K": K, "omega": w, "mu": mu, "sigma": S}
+
+
+def warm_targets(mix, frame):
+    K = _c(mix["K"], np.int32)
+    w = _c(mix["omega"], np.float64)
+    kmax = w.shape[1]
+    fr = _c(frame, np.float64)
+    n_cells = len(K)
+    Tg = np.zeros((n_cells, NO))
+    lib().orc_warm_targets(_p(K), _p(w), _p(_c(mix["mu"], np.float64)), _p(_c(mix["sigma"], np.float64)), _p(fr),
+                           n_cells, kmax, _p(Tg))
+    return Tg
