@@ -97,7 +97,13 @@ typedef struct gm_mix {
 
 /* Optional initial mixtures (learned warm start).  Cells with K[c] > 0
  * start from them instead of the random cold start; mu in the same
- * coordinates as v.  Same layout as gm_mix. */
+ * coordinates as v.  Same layout as gm_mix; K[c] <= kmax, and the caller
+ * keeps n w_k > T/2 for every supplied component (gm_warm_decode does).
+ * When running to convergence, a cell whose warm-started penalised
+ * likelihood ends below that of the single Gaussian with its moments, less
+ * 1e-5 of its magnitude, is fitted again from the cold start and flagged
+ * GM_ST_WARM_FALLBACK (its other flags are the cold fit's; visits count
+ * both fits). */
 typedef struct gm_init {
     const int32_t* K;
     const double* omega;
@@ -165,6 +171,99 @@ int gm_reconstruct(const int32_t* K, const double* omega, const double* mu, cons
                    const int64_t* out_off, const double* target, int64_t n_cells, int32_t D, int32_t dx,
                    uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status, void* ws,
                    size_t ws_bytes, void* stream);
+
+/* ---- learned warm start ----
+ * The paper starts every cell's EM from random particles (Sec. 2.3) and
+ * notes that the iteration converges slowly from poor starting points while
+ * better ones speed it up (Sec. 3.4).  The warm start maps per-cell features
+ * of the velocity distribution to an initial mixture (a gm_init record) with
+ * a 105 -> 256 -> 256 -> 160 perceptron (ReLU hidden layers) whose products
+ * run on BF16 matrix cores with FP32 accumulation.  gm_compress keeps a warm
+ * start only if its converged penalised likelihood is at least that of the
+ * single Gaussian with the cell's moments; otherwise it refits the cell from
+ * the cold start and sets GM_ST_WARM_FALLBACK.  Only D = 3 is built.
+ *
+ * Features (105 per cell, stored as BF16 bit patterns in rows of 128, the
+ * last 23 zero): with m, C the cell's weighted mean and covariance and
+ * C = L_C L_C^T, the whitened velocities u = L_C^-1 (v - m); three 32-bin
+ * histograms of u_x, u_y, u_z over [-4, 4) (bin width 1/4, values outside
+ * clamped to the end bins) weighted by alpha/W; E[u_d^3] (3); E[u_d^4] - 3
+ * (3); E[u_x^2 u_y^2] - 1, E[u_x^2 u_z^2] - 1, E[u_y^2 u_z^2] - 1, all
+ * expectations weighted by alpha/W.  The frame record (9 doubles per cell)
+ * is m (3) and L_C packed lower row-major (00, 10, 11, 20, 21, 22); a cell
+ * that is empty or has a singular covariance gets zero features and a zero
+ * factor, and decodes to K = 0 (cold start).
+ *
+ * Network output (160 FP32 per cell): 16 slots of (logit, mu_hat[3],
+ * ln l00, l10, ln l11, l20, l21, ln l22) in the whitened frame.  Decode:
+ * w = softmax(logits); keep, in slot order, the slots with n w > T/2 (at most
+ * kmax; if none, the most probable), renormalise their weights; mu = m +
+ * L_C mu_hat; Sigma = (L_C L_hat)(L_C L_hat)^T.
+ *
+ * Training targets (160 FP32 per cell): a fitted mixture in the same frame
+ * and slot layout (weight in place of the logit), slots sorted by weight
+ * descending (ties by mu_hat_x ascending), unused slots zero.  Loss per
+ * batch of B cells: (1/B) sum over cells of the soft cross-entropy
+ * -sum_j w_t,j ln softmax_j plus lambda sum_j w_t,j (|mu_hat_j - mu_t,j|^2 +
+ * |l_j - l_t,j|^2) over the 9 non-logit slot entries.  Optimiser: Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights; the products
+ * use BF16 copies refreshed after every step.
+ *
+ * Parameters (gm_warm_param_count() FP32 values, the layout of get/set):
+ * W1 [128][256] (rows 105..127 unused), b1 [256], W2 [256][256], b2 [256],
+ * W3 [256][160], b3 [160]; weight matrices row-major [in][out].
+ */
+typedef struct gm_warm gm_warm;
+
+size_t gm_warm_param_count(void);
+
+/* Create a model with Glorot-uniform weights drawn from Philox4x64-10
+ * (key (seed, "WARM"), counter (index, tensor, 0, 0)) and zero biases, and
+ * training buffers for batches of `batch` cells (1 <= batch <= 2^20).
+ * Allocates device memory on the current device; D must be 3. */
+int gm_warm_create(gm_warm** model, int32_t D, int32_t kmax, int32_t batch, uint64_t seed, void* stream);
+/* Free the model (waits for the device). */
+void gm_warm_destroy(gm_warm* model);
+/* Copy the FP32 parameters to / from HOST memory of gm_warm_param_count()
+ * floats (synchronous).  set_params also resets the Adam state. */
+int gm_warm_get_params(const gm_warm* model, float* host);
+int gm_warm_set_params(gm_warm* model, const float* host);
+/* Copy the gradient of the last gm_warm_train_step to HOST memory
+ * (synchronous; same layout as the parameters). */
+int gm_warm_gradients(const gm_warm* model, float* host);
+
+/* Features and frames of n_cells D = 3 cells (device arrays):
+ *   v, alpha, cell_off  as for gm_compress
+ *   feats  [n_cells * 128] uint16 BF16 bit patterns
+ *   frame  [n_cells * 9] FP64 */
+int gm_warm_features(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, int32_t D,
+                     uint16_t* feats, double* frame, void* stream);
+
+/* Network outputs Y [n_rows * 160] FP32 for features [n_rows * 128] BF16;
+ * ws: device workspace of at least gm_warm_forward_workspace(n_rows) bytes. */
+size_t gm_warm_forward_workspace(int64_t n_rows);
+int gm_warm_forward(const gm_warm* model, const uint16_t* feats, int64_t n_rows, float* Y, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Decode Y into initial mixtures (gm_init layout, kmax slots; K = 0 where
+ * the frame has no factor).  cell_off gives the cell sizes n. */
+int gm_warm_decode(const float* Y, const double* frame, const int64_t* cell_off, int64_t n_cells, int32_t kmax,
+                   int32_t* K, double* omega, double* mu, double* sigma, void* stream);
+
+/* Training targets [n_cells * 160] FP32 from fitted mixtures (gm_mix
+ * layout, kmax slots) and frames.  A component whose whitened covariance
+ * does not factor gets L_hat = 1e-3 I. */
+int gm_warm_targets(const int32_t* K, const double* omega, const double* mu, const double* sigma, int32_t kmax,
+                    const double* frame, int64_t n_cells, float* targets, void* stream);
+
+/* One Adam step on the rows idx[0..batch-1] (device int32) of feats
+ * [n_rows * 128] BF16 and targets [n_rows * 160] FP32, learning rate lr > 0,
+ * loss weight lambda >= 0.  An index outside [0, n_rows) contributes a zero
+ * row (no loss, no gradient).  loss_rows: nullable device [batch] FP32
+ * receiving each row's loss term (the batch loss is their sum divided by
+ * batch).  Calls on one model must not overlap. */
+int gm_warm_train_step(gm_warm* model, const uint16_t* feats, const float* targets, int64_t n_rows,
+                       const int32_t* idx, float lr, float lambda, float* loss_rows, void* stream);
 
 /* ---- diagnostics ----
  * Phase timing for benchmarks.  While enabled, gm_compress records HIP

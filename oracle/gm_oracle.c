@@ -471,118 +471,141 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
         return;
     }
 
-    if (have_init) {
-        /* supplied initial mixture (learned warm start or a test's fixed init) */
-        int K0 = J->init_K[c];
-        if (K0 > J->kmax) K0 = J->kmax;
-        m.K = K0;
-        for (int k = 0; k < K0; ++k) {
-            size_t s = (size_t)c * J->kmax + k;
-            m.w[k] = J->init_w[s];
-            for (int i = 0; i < D; ++i) m.mu[k][i] = J->init_mu[s * D + i] - mean[i];
-            unpack_sym(D, J->init_S + s * nt, m.S[k]);
-            if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
-        }
-        renormalise(&m);
-    } else {
-        /* O3: cold start (Sec. 2.3): K0 components, each mean at a distinct
-         * randomly chosen particle, each covariance the whole cell's covariance,
-         * equal weights.  K0 is capped so that N - T K0 / 2 > 0 in eq. (omegak). */
-        int K0 = J->kmax < n ? J->kmax : n;
-        if (T > 0.0) {
-            double cap = floor(N / T);
-            if (cap < 1.0) cap = 1.0;
-            if ((double)K0 > cap) {
-                K0 = (int)cap;
-                status |= ORC_K0_CAPPED;
-            }
-        }
-        /* partial Fisher-Yates over particle indices; draw j uses Philox with
-         * key (seed, "INIT") and counter (j, cell, 0, 0); the index offset is
-         * floor(x * (n - j) / 2^64) of the first 64-bit output x. */
-        int* perm = (int*)malloc(sizeof(int) * (size_t)n);
-        orc_init_indices(n, K0, J->seed, (uint64_t)c, perm);
-        m.K = K0;
-        for (int k = 0; k < K0; ++k) {
-            m.w[k] = 1.0 / K0;
-            for (int i = 0; i < D; ++i) m.mu[k][i] = x[(size_t)perm[k] * D + i];
-            memcpy(m.S[k], C, sizeof(C));
-            memcpy(m.L[k], LC, sizeof(LC));
-        }
-        free(perm);
-    }
-
-    /* O4-O6: component-wise adaptive EM sweeps (Sec. 2.3 steps 1-4) */
+    /* A warm start (the paper starts cold, Sec. 2.3; a better start only
+     * speeds the iteration up, Sec. 3.4) is accepted when its converged
+     * penalised likelihood is at least that of the single Gaussian with the
+     * cell's own moments, less 1e-5 of its magnitude (so that a warm start
+     * that converges to that single Gaussian is kept whatever the rounding);
+     * otherwise the cell is fitted again from the cold start and flagged.  Replay mode (fixed sweep counts) never restarts. */
     const int fixed = J->fixed_sweeps ? J->fixed_sweeps[c] : 0;
-    const int standard = (J->mode & ORC_MODE_STANDARD_EM) != 0;
-    const int cap_sweeps = fixed > 0 ? fixed : J->max_sweeps;
-    double L_prev = 0.0, L_s = 0.0;
-    int s = 0;
-    int64_t visits = 0;
-    const double half_T = 0.5 * T;
-    for (s = 1; s <= cap_sweeps; ++s) {
-        int annihilated = 0;
-        if (standard) {
-            /* plain EM: joint E-step, then every component's M-step with
-             * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
-            double* gk = g;
-            mixture next = m;
-            double gp[ORC_MAXK];
-            for (int p = 0; p < n; ++p) {
-                particle_responsibilities(D, &m, x + (size_t)p * D, a[p], gp);
-                for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = gp[k];
-            }
-            for (int k = 0; k < m.K; ++k) {
-                double Nk = 0.0;
-                for (int p = 0; p < n; ++p) Nk += gk[(size_t)k * n + p];
-                mean_cov(D, n, x, gk + (size_t)k * n, Nk, next.mu[k], next.S[k]);
-                next.w[k] = Nk / N;
-                if (factor_component(D, &next, k, trC)) status |= ORC_COV_FLOOR;
-            }
-            visits += m.K;
-            m = next;
-        } else {
-            int k = 0;
-            while (k < m.K) {
-                /* step 1: E-step for component k with the current parameters */
-                responsibilities(D, &m, k, n, x, a, g);
-                double Nk = 0.0;
-                for (int p = 0; p < n; ++p) Nk += g[p];
-                ++visits;
-                if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
-                /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
-                if (Nk - half_T <= 0.0) {
-                    remove_component(&m, k);
-                    renormalise(&m);
-                    annihilated = 1;
-                    continue;
-                }
-                mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
-                /* eq. (omegak) with K the current number of live components */
-                m.w[k] = (Nk - half_T) / (N - half_T * m.K);
-                /* step 3: renormalise */
-                renormalise(&m);
-                if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
-                ++k;
-            }
-        }
-        /* step 4: monitor the penalised log-likelihood */
-        L_s = penalised_L(D, T, &m, n, x, a, N);
-        if (J->L_trace) J->L_trace[(size_t)c * J->max_sweeps + (s - 1)] = L_s;
-        if (J->K_trace) J->K_trace[(size_t)c * J->max_sweeps + (s - 1)] = m.K;
-        if (fixed > 0) {
-            if (s == fixed) break;
-            L_prev = L_s;
-            continue;
-        }
-        if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
-        if (s == J->max_sweeps) {
-            status |= ORC_MAXSWEEPS;
-            break;
-        }
-        L_prev = L_s;
+    double L_one = 0.0;
+    if (have_init) {
+        mixture one;
+        memset(&one, 0, sizeof(one));
+        one.K = 1;
+        one.w[0] = 1.0;
+        memcpy(one.S[0], C, sizeof(C));
+        memcpy(one.L[0], LC, sizeof(LC));
+        L_one = penalised_L(D, T, &one, n, x, a, N);
     }
-    if (s > cap_sweeps) s = cap_sweeps;
+    int64_t visits = 0;
+    double L_s = 0.0;
+    int s = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (have_init) {
+            /* supplied initial mixture (learned warm start or a test's fixed init) */
+            int K0 = J->init_K[c];
+            if (K0 > J->kmax) K0 = J->kmax;
+            m.K = K0;
+            for (int k = 0; k < K0; ++k) {
+                size_t s = (size_t)c * J->kmax + k;
+                m.w[k] = J->init_w[s];
+                for (int i = 0; i < D; ++i) m.mu[k][i] = J->init_mu[s * D + i] - mean[i];
+                unpack_sym(D, J->init_S + s * nt, m.S[k]);
+                if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+            }
+            renormalise(&m);
+        } else {
+            /* O3: cold start (Sec. 2.3): K0 components, each mean at a distinct
+             * randomly chosen particle, each covariance the whole cell's covariance,
+             * equal weights.  K0 is capped so that N - T K0 / 2 > 0 in eq. (omegak). */
+            int K0 = J->kmax < n ? J->kmax : n;
+            if (T > 0.0) {
+                double cap = floor(N / T);
+                if (cap < 1.0) cap = 1.0;
+                if ((double)K0 > cap) {
+                    K0 = (int)cap;
+                    status |= ORC_K0_CAPPED;
+                }
+            }
+            /* partial Fisher-Yates over particle indices; draw j uses Philox with
+             * key (seed, "INIT") and counter (j, cell, 0, 0); the index offset is
+             * floor(x * (n - j) / 2^64) of the first 64-bit output x. */
+            int* perm = (int*)malloc(sizeof(int) * (size_t)n);
+            orc_init_indices(n, K0, J->seed, (uint64_t)c, perm);
+            m.K = K0;
+            for (int k = 0; k < K0; ++k) {
+                m.w[k] = 1.0 / K0;
+                for (int i = 0; i < D; ++i) m.mu[k][i] = x[(size_t)perm[k] * D + i];
+                memcpy(m.S[k], C, sizeof(C));
+                memcpy(m.L[k], LC, sizeof(LC));
+            }
+            free(perm);
+        }
+
+        /* O4-O6: component-wise adaptive EM sweeps (Sec. 2.3 steps 1-4) */
+        const int standard = (J->mode & ORC_MODE_STANDARD_EM) != 0;
+        const int cap_sweeps = fixed > 0 ? fixed : J->max_sweeps;
+        double L_prev = 0.0;
+        const double half_T = 0.5 * T;
+        for (s = 1; s <= cap_sweeps; ++s) {
+            int annihilated = 0;
+            if (standard) {
+                /* plain EM: joint E-step, then every component's M-step with
+                 * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
+                double* gk = g;
+                mixture next = m;
+                double gp[ORC_MAXK];
+                for (int p = 0; p < n; ++p) {
+                    particle_responsibilities(D, &m, x + (size_t)p * D, a[p], gp);
+                    for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = gp[k];
+                }
+                for (int k = 0; k < m.K; ++k) {
+                    double Nk = 0.0;
+                    for (int p = 0; p < n; ++p) Nk += gk[(size_t)k * n + p];
+                    mean_cov(D, n, x, gk + (size_t)k * n, Nk, next.mu[k], next.S[k]);
+                    next.w[k] = Nk / N;
+                    if (factor_component(D, &next, k, trC)) status |= ORC_COV_FLOOR;
+                }
+                visits += m.K;
+                m = next;
+            } else {
+                int k = 0;
+                while (k < m.K) {
+                    /* step 1: E-step for component k with the current parameters */
+                    responsibilities(D, &m, k, n, x, a, g);
+                    double Nk = 0.0;
+                    for (int p = 0; p < n; ++p) Nk += g[p];
+                    ++visits;
+                    if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
+                    /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
+                    if (Nk - half_T <= 0.0) {
+                        remove_component(&m, k);
+                        renormalise(&m);
+                        annihilated = 1;
+                        continue;
+                    }
+                    mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
+                    /* eq. (omegak) with K the current number of live components */
+                    m.w[k] = (Nk - half_T) / (N - half_T * m.K);
+                    /* step 3: renormalise */
+                    renormalise(&m);
+                    if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+                    ++k;
+                }
+            }
+            /* step 4: monitor the penalised log-likelihood */
+            L_s = penalised_L(D, T, &m, n, x, a, N);
+            if (J->L_trace) J->L_trace[(size_t)c * J->max_sweeps + (s - 1)] = L_s;
+            if (J->K_trace) J->K_trace[(size_t)c * J->max_sweeps + (s - 1)] = m.K;
+            if (fixed > 0) {
+                if (s == fixed) break;
+                L_prev = L_s;
+                continue;
+            }
+            if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
+            if (s == J->max_sweeps) {
+                status |= ORC_MAXSWEEPS;
+                break;
+            }
+            L_prev = L_s;
+        }
+        if (s > cap_sweeps) s = cap_sweeps;
+        if (!have_init || fixed > 0 || L_s >= L_one - 1e-5 * fabs(L_one)) break;
+        /* rejected warm start: cold start, flags of the cold fit only */
+        have_init = 0;
+        status = ORC_WARM_FALLBACK;
+    }
     J->sweeps[c] = s;
     J->visits[c] = visits;
     J->L_pen[c] = L_s;

@@ -19,7 +19,8 @@
  *     the diagonal entries of the lower factor L_hat as logarithms.
  *   decode: w = softmax(logit); keep slots with N w > T/2 (slot order; if
  *     none, the largest), renormalise; mu = m + L_C mu_hat; Sigma = L L^T with
- *     L = L_C L_hat.
+ *     L = L_C L_hat.  A cell without a frame (empty, or a singular
+ *     covariance) decodes to K = 0: it keeps the cold start.
  *   loss: soft cross-entropy of the target weights against softmax(logit)
  *     plus lambda sum_j w_t,j (|mu_hat_j - mu_t,j|^2 + |l_j - l_t,j|^2),
  *     averaged over the batch; targets are the plain-EM mixtures expressed in
@@ -274,6 +275,18 @@ int orc_warm_decode(const double* Y, const double* frame, const int64_t* off, in
         const double* y = Y + (size_t)c * NO;
         const double* fr = frame + (size_t)c * 9;
         const double N = (double)(off[c + 1] - off[c]);
+        for (int q = 0; q < kmax; ++q) {
+            size_t s = (size_t)c * kmax + q;
+            w[s] = 0;
+            for (int d = 0; d < 3; ++d) mu[s * 3 + d] = 0;
+            for (int d = 0; d < 6; ++d) S[s * 6 + d] = 0;
+        }
+        /* no whitening frame (empty cell or singular covariance): no warm
+         * start, the cell keeps the cold start */
+        if (!(fr[3] > 0)) {
+            K[c] = 0;
+            continue;
+        }
         double mx = -INFINITY;
         for (int j = 0; j < NSLOT; ++j)
             if (y[j * SLOT] > mx) mx = y[j * SLOT];
@@ -294,12 +307,8 @@ int orc_warm_decode(const double* Y, const double* frame, const int64_t* off, in
         for (int q = 0; q < nk; ++q) ws += p[keep[q]];
         double LC[3][3] = {{fr[3], 0, 0}, {fr[4], fr[5], 0}, {fr[6], fr[7], fr[8]}};
         K[c] = nk;
-        for (int q = 0; q < kmax; ++q) {
+        for (int q = 0; q < nk; ++q) {
             size_t s = (size_t)c * kmax + q;
-            w[s] = 0;
-            for (int d = 0; d < 3; ++d) mu[s * 3 + d] = 0;
-            for (int d = 0; d < 6; ++d) S[s * 6 + d] = 0;
-            if (q >= nk) continue;
             const double* o = y + keep[q] * SLOT;
             w[s] = p[keep[q]] / ws;
             for (int d = 0; d < 3; ++d) {

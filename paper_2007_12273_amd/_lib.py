@@ -40,7 +40,10 @@ class GmInit(ctypes.Structure):
 
 
 EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_reconstruct_workspace",
-           "gm_reconstruct", "gm_profile_enable", "gm_profile_read", "gm_strerror", "gm_version")
+           "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
+           "gm_warm_set_params", "gm_warm_gradients", "gm_warm_features", "gm_warm_forward_workspace",
+           "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_profile_enable",
+           "gm_profile_read", "gm_strerror", "gm_version")
 
 _lib = None
 
@@ -69,6 +72,28 @@ def load():
     L.gm_reconstruct.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_uint64, P, P, P, P, P, ctypes.c_size_t, P]
     L.gm_reconstruct.restype = ctypes.c_int
+    I32, I64, SZ, U64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_float
+    L.gm_warm_param_count.argtypes = []
+    L.gm_warm_param_count.restype = SZ
+    L.gm_warm_create.argtypes = [ctypes.POINTER(P), I32, I32, I32, U64, P]
+    L.gm_warm_create.restype = ctypes.c_int
+    L.gm_warm_destroy.argtypes = [P]
+    L.gm_warm_destroy.restype = None
+    for name in ("gm_warm_get_params", "gm_warm_set_params", "gm_warm_gradients"):
+        getattr(L, name).argtypes = [P, P]
+        getattr(L, name).restype = ctypes.c_int
+    L.gm_warm_features.argtypes = [P, P, P, I64, I32, P, P, P]
+    L.gm_warm_features.restype = ctypes.c_int
+    L.gm_warm_forward_workspace.argtypes = [I64]
+    L.gm_warm_forward_workspace.restype = SZ
+    L.gm_warm_forward.argtypes = [P, P, I64, P, P, SZ, P]
+    L.gm_warm_forward.restype = ctypes.c_int
+    L.gm_warm_decode.argtypes = [P, P, P, I64, I32, P, P, P, P, P]
+    L.gm_warm_decode.restype = ctypes.c_int
+    L.gm_warm_targets.argtypes = [P, P, P, P, I32, P, I64, P, P]
+    L.gm_warm_targets.restype = ctypes.c_int
+    L.gm_warm_train_step.argtypes = [P, P, P, I64, P, F32, F32, P, P]
+    L.gm_warm_train_step.restype = ctypes.c_int
     L.gm_profile_enable.argtypes = [ctypes.c_int]
     L.gm_profile_enable.restype = None
     L.gm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]

@@ -171,3 +171,195 @@ def profile_read():
     buf = (ctypes.c_double * 4)()
     check(_lib.load().gm_profile_read(buf, 4), "gm_profile_read")
     return dict(zip(("plan", "em", "finish", "reconstruct"), list(buf)))
+
+
+# ---------------------------------------------------------------------------
+# learned warm start
+# ---------------------------------------------------------------------------
+NFEAT_ROW, NOUT = 128, 160
+PARAM_SHAPES = (("W1", (128, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (256, 160)),
+                ("b3", (160,)))
+
+
+def warm_features(v, alpha, cell_off, feats=None, frame=None, stream=None):
+    """Features [n_cells, 128] (int16 tensor holding BF16 bit patterns) and
+    frames [n_cells, 9] FP64 of 3V cells (into feats / frame when given)."""
+    _need(v, torch.float64, "v")
+    _need(alpha, torch.float64, "alpha")
+    _need(cell_off, torch.int64, "cell_off")
+    n_cells = cell_off.numel() - 1
+    if feats is None:
+        feats = torch.empty(n_cells, NFEAT_ROW, dtype=torch.int16, device=v.device)
+    if frame is None:
+        frame = torch.empty(n_cells, 9, dtype=torch.float64, device=v.device)
+    _need(feats, torch.int16, "feats")
+    _need(frame, torch.float64, "frame")
+    if feats.shape != (n_cells, NFEAT_ROW) or frame.shape != (n_cells, 9):
+        raise ValueError("feats must be [n_cells, 128] and frame [n_cells, 9]")
+    rc = _lib.load().gm_warm_features(_ptr(v), _ptr(alpha), _ptr(cell_off), n_cells, 3, _ptr(feats), _ptr(frame),
+                                      _stream(stream))
+    check(rc, "gm_warm_features")
+    return feats, frame
+
+
+def warm_targets(mix, frame, stream=None):
+    """Training targets [n_cells, 160] FP32 from a compress record."""
+    K, omega, mu, sigma = mix["K"], mix["omega"], mix["mu"], mix["sigma"]
+    _need(K, torch.int32, "K")
+    for t, name in ((omega, "omega"), (mu, "mu"), (sigma, "sigma"), (frame, "frame")):
+        _need(t, torch.float64, name)
+    n_cells, kmax = omega.shape
+    T = torch.empty(n_cells, NOUT, dtype=torch.float32, device=omega.device)
+    rc = _lib.load().gm_warm_targets(_ptr(K), _ptr(omega), _ptr(mu), _ptr(sigma), kmax, _ptr(frame), n_cells,
+                                     _ptr(T), _stream(stream))
+    check(rc, "gm_warm_targets")
+    return T
+
+
+def warm_decode(Y, frame, cell_off, kmax, out=None, stream=None):
+    """Initial mixtures (gm_init layout) from network outputs."""
+    _need(Y, torch.float32, "Y")
+    _need(frame, torch.float64, "frame")
+    _need(cell_off, torch.int64, "cell_off")
+    n_cells = cell_off.numel() - 1
+    if Y.shape != (n_cells, NOUT) or frame.shape != (n_cells, 9):
+        raise ValueError("Y must be [n_cells, 160] and frame [n_cells, 9]")
+    dev = Y.device
+    if out is None:
+        out = {"K": torch.empty(n_cells, dtype=torch.int32, device=dev),
+               "omega": torch.empty(n_cells, kmax, dtype=torch.float64, device=dev),
+               "mu": torch.empty(n_cells, kmax, 3, dtype=torch.float64, device=dev),
+               "sigma": torch.empty(n_cells, kmax, 6, dtype=torch.float64, device=dev)}
+    rc = _lib.load().gm_warm_decode(_ptr(Y), _ptr(frame), _ptr(cell_off), n_cells, kmax, _ptr(out["K"]),
+                                    _ptr(out["omega"]), _ptr(out["mu"]), _ptr(out["sigma"]), _stream(stream))
+    check(rc, "gm_warm_decode")
+    return out
+
+
+class WarmStart:
+    """Handle of a gm_warm model (the perceptron and its training state)."""
+
+    def __init__(self, kmax, batch=1024, seed=0, device="cuda"):
+        L = _lib.load()
+        self.kmax, self.batch, self.device = kmax, batch, torch.device(device)
+        self.n_param = int(L.gm_warm_param_count())
+        h = ctypes.c_void_p()
+        check(L.gm_warm_create(ctypes.byref(h), 3, kmax, batch, seed, _stream(None)), "gm_warm_create")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            _lib.load().gm_warm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        """Parameters as a flat float32 numpy array (host copy)."""
+        import numpy as np
+        buf = np.empty(self.n_param, dtype=np.float32)
+        check(_lib.load().gm_warm_get_params(self._h, buf.ctypes.data), "gm_warm_get_params")
+        return buf
+
+    def set_params(self, flat):
+        import numpy as np
+        buf = np.ascontiguousarray(flat, dtype=np.float32)
+        if buf.size != self.n_param:
+            raise ValueError("expected %d parameters" % self.n_param)
+        check(_lib.load().gm_warm_set_params(self._h, buf.ctypes.data), "gm_warm_set_params")
+
+    def gradients(self):
+        import numpy as np
+        buf = np.empty(self.n_param, dtype=np.float32)
+        check(_lib.load().gm_warm_gradients(self._h, buf.ctypes.data), "gm_warm_gradients")
+        return buf
+
+    def forward(self, feats, Y=None, stream=None):
+        _need(feats, torch.int16, "feats")
+        n = feats.shape[0]
+        if feats.shape[1] != NFEAT_ROW:
+            raise ValueError("features must be [n, 128]")
+        if Y is not None:
+            _need(Y, torch.float32, "Y")
+            if Y.shape != (n, NOUT):
+                raise ValueError("Y must be [n, 160]")
+        L = _lib.load()
+        self.forward_workspace(n)
+        if Y is None:
+            Y = torch.empty(n, NOUT, dtype=torch.float32, device=feats.device)
+        check(L.gm_warm_forward(self._h, _ptr(feats), n, _ptr(Y), _ptr(self._ws), self._ws.numel(), _stream(stream)),
+              "gm_warm_forward")
+        return Y
+
+    def train_step(self, feats, targets, idx, lr=1e-3, lam=1.0, loss_rows=None, stream=None):
+        _need(feats, torch.int16, "feats")
+        _need(targets, torch.float32, "targets")
+        _need(idx, torch.int32, "idx")
+        if idx.numel() != self.batch:
+            raise ValueError("idx must hold exactly batch = %d rows" % self.batch)
+        if feats.shape[1] != NFEAT_ROW or targets.shape != (feats.shape[0], NOUT):
+            raise ValueError("features must be [n, 128] and targets [n, 160]")
+        if loss_rows is not None:
+            _need(loss_rows, torch.float32, "loss_rows")
+            if loss_rows.numel() < self.batch:
+                raise ValueError("loss_rows must hold batch = %d values" % self.batch)
+        check(_lib.load().gm_warm_train_step(self._h, _ptr(feats), _ptr(targets), feats.shape[0], _ptr(idx), lr, lam,
+                                             _ptr(loss_rows), _stream(stream)), "gm_warm_train_step")
+
+    def initial_mixtures(self, v, alpha, cell_off, bufs=None, stream=None):
+        """features -> forward -> decode: a gm_init record for compress.
+        `bufs` (from init_buffers) makes repeated calls allocation-free."""
+        n_cells = cell_off.numel() - 1
+        if bufs is None:
+            bufs = self.init_buffers(n_cells)
+        warm_features(v, alpha, cell_off, feats=bufs["feats"], frame=bufs["frame"], stream=stream)
+        self.forward(bufs["feats"], Y=bufs["Y"], stream=stream)
+        return warm_decode(bufs["Y"], bufs["frame"], cell_off, self.kmax, out=bufs["init"], stream=stream)
+
+    def init_buffers(self, n_cells):
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.forward_workspace(n_cells)
+        return {"feats": torch.empty(n_cells, NFEAT_ROW, dtype=torch.int16, device=dev),
+                "frame": torch.empty(n_cells, 9, **f64),
+                "Y": torch.empty(n_cells, NOUT, dtype=torch.float32, device=dev),
+                "init": {"K": torch.empty(n_cells, dtype=torch.int32, device=dev),
+                         "omega": torch.empty(n_cells, self.kmax, **f64),
+                         "mu": torch.empty(n_cells, self.kmax, 3, **f64),
+                         "sigma": torch.empty(n_cells, self.kmax, 6, **f64)}}
+
+    def forward_workspace(self, n):
+        need = int(_lib.load().gm_warm_forward_workspace(n))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+
+
+def params_to_flat(P):
+    """Oracle-layout parameters (W1 [105, 256], ...) -> flat float32 vector
+    of the library's layout (W1 padded to 128 rows)."""
+    import numpy as np
+    parts = []
+    for name, shape in PARAM_SHAPES:
+        a = np.asarray(P[name], dtype=np.float64)
+        if name == "W1":
+            z = np.zeros(shape)
+            z[:a.shape[0]] = a
+            a = z
+        parts.append(a.reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def flat_to_params(flat):
+    out, o = {}, 0
+    for name, shape in PARAM_SHAPES:
+        n = 1
+        for s in shape:
+            n *= s
+        out[name] = flat[o:o + n].reshape(shape)
+        o += n
+    return out

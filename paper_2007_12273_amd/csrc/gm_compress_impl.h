@@ -461,290 +461,305 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
             }
         }
 
-        // ---------------- initial mixture ------------------------------------
-        int K = 0;
-        const bool warm = A.init.K != nullptr && A.init.K[c] > 0;
-        if (tid == 0) s_flag = 0;
-        if (warm) {
-            K = min(A.init.K[c], kmax);
-        } else {
-            K = min(kmax, n);
-            const int cap = max(1, (int)floor(N / T));
-            if (K > cap) {
-                K = cap;
-                status |= GM_ST_K0_CAPPED;
-            }
-        }
-        __syncthreads();
-        if (tid < K) {
-            CompState<R, D> cs;
-            if (warm) {
-                const size_t s0 = (size_t)c * kmax;
-                double wsum = 0.0;
-                for (int j = 0; j < K; ++j) wsum += A.init.omega[s0 + j];
-                const size_t sk = s0 + tid;
-#pragma unroll
-                for (int d = 0; d < D; ++d) cs.mu[d] = (R)(A.init.mu[sk * D + d] - ci->m[d]);
-#pragma unroll
-                for (int q = 0; q < NT; ++q) cs.S[q] = (R)A.init.sigma[sk * NT + q];
-                cs.u = (R)(A.init.omega[sk] / wsum);
-            } else {
-                const int ip = A.init_idx[(size_t)c * kInitSlots + tid];
-#pragma unroll
-                for (int d = 0; d < D; ++d) cs.mu[d] = (R)(vc[(size_t)ip * D + d] - ci->m[d]);
-#pragma unroll
-                for (int q = 0; q < NT; ++q) cs.S[q] = (R)ci->C[q];
-                cs.u = (R)(1.0 / K);
-            }
-            if (factor_comp<R, D>(cs, trC, sdc)) s_flag = 1;
-            for (int w = 0; w < nwaves; ++w) compw[w][tid] = cs;
-        }
-        __syncthreads();
-        if (s_flag) status |= GM_ST_COV_FLOOR;
-        R G = R(0);
-        for (int j = 0; j < K; ++j) G += comp[j].u;
-
-        // ---------------- initial density terms ------------------------------
-        if constexpr (STORE_E) {
-            for (int j = 0; j < K; ++j) {
-                const CompState<R, D> cj = comp[j];
-#pragma unroll
-                for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                R mx = e[p][0];
-#pragma unroll
-                for (int j = 1; j < KMAX; ++j)
-                    if (j < K) mx = fmax(mx, e[p][j]);
-                ref[p] = mx;
-#pragma unroll
-                for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
-                Sden[p] = resum(e[p]);
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                R mx = R(-1e30);
-                for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
-                R s = R(0);
-                for (int j = 0; j < K; ++j) s += fast_exp2(log2_term<R, D>(comp[j], x[p]) - mx);
-                ref[p] = mx;
-                Sden[p] = s;
-            }
-        }
-
-        // ---------------- sweeps ---------------------------------------------
+        // A warm start is kept when its converged penalised likelihood is at
+        // least that of the single Gaussian with the cell's own moments,
+        // sum_p a_p ln N(x_p; 0, C) - (T/2) ln N = N (lnc0 - D/2) - (T/2) ln N
+        // (sum_p a_p x_p x_p^T = N C), less 1e-5 of its magnitude; otherwise
+        // the cell is fitted again from the cold start.  Replay mode (fixed sweep counts) never restarts.
         const int fixed = A.fixed ? A.fixed[c] : 0;
-        const int max_sweeps = A.max_sweeps;
-        const double tol = A.tol;
-        const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
-        int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
-        uint32_t alive = (1u << K) - 1u;
-        double L_prev = 0.0, L_s = 0.0;
-        int s = 0;
+        const double L_one = N * (lnc0 - 0.5 * D) - halfT * log(N);
+        bool warm = A.init.K != nullptr && A.init.K[c] > 0;
         long long visits = 0;
-        for (s = 1; s <= cap_sweeps; ++s) {
-            bool annihilated = false;
-            for (int k = 0; k < Kslots; ++k) {
-                if (!((alive >> k) & 1u)) continue;
-                ++visits;
-                R ckmu[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
-                const R cku = comp[k].u;
-                // E-step of k with the current parameters of every component,
-                // and the M-step sums about the current mean of k
-                R sums[NS];
-#pragma unroll
-                for (int t = 0; t < NS; ++t) sums[t] = R(0);
-                [[maybe_unused]] R eold[STORE_E ? 1 : P];
-                auto accumulate = [&](int p, R ek, R den) {
-                    const R inv = den > R(0) ? fast_rcp(den) : R(0);
-                    const R g = a[p] * ek * inv;
-                    R d[D];
-#pragma unroll
-                    for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
-                    sums[0] += g;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        const R gd = g * d[i];
-                        sums[1 + i] += gd;
-#pragma unroll
-                        for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
-                    }
-                };
-                if constexpr (STORE_E) {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
-                } else {
-                    const CompState<R, D> ck = comp[k];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
-                        accumulate(p, eold[p], Sden[p]);
-                    }
+        double L_s = 0.0;
+        int s = 0;
+        int K = 0;
+        R G = R(0);
+        for (;;) {
+            // ---------------- initial mixture ------------------------------------
+            if (tid == 0) s_flag = 0;
+            if (warm) {
+                K = min(A.init.K[c], kmax);
+            } else {
+                K = min(kmax, n);
+                const int cap = max(1, (int)floor(N / T));
+                if (K > cap) {
+                    K = cap;
+                    status |= GM_ST_K0_CAPPED;
                 }
-                block_sum<NS>(sums, red_r, par_r, nwaves);
-                const R Nk = sums[0];
-                const R NkT = Nk - (R)halfT;
-                if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
-                if (NkT <= R(0)) {
-                    // annihilate k (eq. omegak); the weights renormalise through G
-                    alive &= ~(1u << k);
-                    G -= cku;
-                    --K;
-                    annihilated = true;
+            }
+            __syncthreads();
+            if (tid < K) {
+                CompState<R, D> cs;
+                if (warm) {
+                    const size_t s0 = (size_t)c * kmax;
+                    double wsum = 0.0;
+                    for (int j = 0; j < K; ++j) wsum += A.init.omega[s0 + j];
+                    const size_t sk = s0 + tid;
+    #pragma unroll
+                    for (int d = 0; d < D; ++d) cs.mu[d] = (R)(A.init.mu[sk * D + d] - ci->m[d]);
+    #pragma unroll
+                    for (int q = 0; q < NT; ++q) cs.S[q] = (R)A.init.sigma[sk * NT + q];
+                    cs.u = (R)(A.init.omega[sk] / wsum);
+                } else {
+                    const int ip = A.init_idx[(size_t)c * kInitSlots + tid];
+    #pragma unroll
+                    for (int d = 0; d < D; ++d) cs.mu[d] = (R)(vc[(size_t)ip * D + d] - ci->m[d]);
+    #pragma unroll
+                    for (int q = 0; q < NT; ++q) cs.S[q] = (R)ci->C[q];
+                    cs.u = (R)(1.0 / K);
+                }
+                if (factor_comp<R, D>(cs, trC, sdc)) s_flag = 1;
+                for (int w = 0; w < nwaves; ++w) compw[w][tid] = cs;
+            }
+            __syncthreads();
+            if (s_flag) status |= GM_ST_COV_FLOOR;
+            G = R(0);
+            for (int j = 0; j < K; ++j) G += comp[j].u;
+
+            // ---------------- initial density terms ------------------------------
+            if constexpr (STORE_E) {
+                for (int j = 0; j < K; ++j) {
+                    const CompState<R, D> cj = comp[j];
+    #pragma unroll
+                    for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
+                }
+    #pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    R mx = e[p][0];
+    #pragma unroll
+                    for (int j = 1; j < KMAX; ++j)
+                        if (j < K) mx = fmax(mx, e[p][j]);
+                    ref[p] = mx;
+    #pragma unroll
+                    for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
+                    Sden[p] = resum(e[p]);
+                }
+            } else {
+    #pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    R mx = R(-1e30);
+                    for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
+                    R s = R(0);
+                    for (int j = 0; j < K; ++j) s += fast_exp2(log2_term<R, D>(comp[j], x[p]) - mx);
+                    ref[p] = mx;
+                    Sden[p] = s;
+                }
+            }
+
+            // ---------------- sweeps ---------------------------------------------
+            const int max_sweeps = A.max_sweeps;
+            const double tol = A.tol;
+            const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
+            int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
+            uint32_t alive = (1u << K) - 1u;
+            double L_prev = 0.0;
+            for (s = 1; s <= cap_sweeps; ++s) {
+                bool annihilated = false;
+                for (int k = 0; k < Kslots; ++k) {
+                    if (!((alive >> k) & 1u)) continue;
+                    ++visits;
+                    R ckmu[D];
+    #pragma unroll
+                    for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
+                    const R cku = comp[k].u;
+                    // E-step of k with the current parameters of every component,
+                    // and the M-step sums about the current mean of k
+                    R sums[NS];
+    #pragma unroll
+                    for (int t = 0; t < NS; ++t) sums[t] = R(0);
+                    [[maybe_unused]] R eold[STORE_E ? 1 : P];
+                    auto accumulate = [&](int p, R ek, R den) {
+                        const R inv = den > R(0) ? fast_rcp(den) : R(0);
+                        const R g = a[p] * ek * inv;
+                        R d[D];
+    #pragma unroll
+                        for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
+                        sums[0] += g;
+    #pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            const R gd = g * d[i];
+                            sums[1 + i] += gd;
+    #pragma unroll
+                            for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
+                        }
+                    };
                     if constexpr (STORE_E) {
-#pragma unroll
+    #pragma unroll
+                        for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
+                    } else {
+                        const CompState<R, D> ck = comp[k];
+    #pragma unroll
                         for (int p = 0; p < P; ++p) {
+                            eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
+                            accumulate(p, eold[p], Sden[p]);
+                        }
+                    }
+                    block_sum<NS>(sums, red_r, par_r, nwaves);
+                    const R Nk = sums[0];
+                    const R NkT = Nk - (R)halfT;
+                    if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
+                    if (NkT <= R(0)) {
+                        // annihilate k (eq. omegak); the weights renormalise through G
+                        alive &= ~(1u << k);
+                        G -= cku;
+                        --K;
+                        annihilated = true;
+                        if constexpr (STORE_E) {
+    #pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const R s_old = Sden[p];
+                                const R s_new = s_old - e[p][k];
+                                e[p][k] = R(0);
+                                // a particle that lost most of its density: re-sum exactly
+                                Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
+                            }
+                        } else {
+    #pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const R s_old = Sden[p];
+                                R s_new = s_old - eold[p];
+                                if (!(s_new > R(1e-4) * s_old)) {
+                                    s_new = R(0);
+                                    for (int j = 0; j < Kslots; ++j)
+                                        if ((alive >> j) & 1u)
+                                            s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                                }
+                                Sden[p] = s_new;
+                            }
+                        }
+                        continue;
+                    }
+                    // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
+                    CompState<R, D> cn;
+                    const R invN = m_rcp(Nk);
+                    R dl[D];
+    #pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        dl[i] = sums[1 + i] * invN;
+                        cn.mu[i] = ckmu[i] + dl[i];
+                    }
+    #pragma unroll
+                    for (int i = 0; i < D; ++i)
+    #pragma unroll
+                        for (int j = i; j < D; ++j)
+                            cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
+                    const R wk = NkT * m_rcp((R)(N - halfT * K));
+                    const R unew = wk * G;
+                    G = G - cku + unew;
+                    cn.u = unew;
+                    if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
+                    if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
+                    if constexpr (STORE_E) {
+    #pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
                             const R s_old = Sden[p];
-                            const R s_new = s_old - e[p][k];
-                            e[p][k] = R(0);
-                            // a particle that lost most of its density: re-sum exactly
+                            const R s_new = s_old - e[p][k] + enew;
+                            e[p][k] = enew;
                             Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
                         }
                     } else {
-#pragma unroll
+    #pragma unroll
                         for (int p = 0; p < P; ++p) {
+                            const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
                             const R s_old = Sden[p];
-                            R s_new = s_old - eold[p];
+                            R s_new = s_old - eold[p] + enew;
                             if (!(s_new > R(1e-4) * s_old)) {
-                                s_new = R(0);
+                                // the particle lost most of its density: re-sum exactly
+                                s_new = enew;
                                 for (int j = 0; j < Kslots; ++j)
-                                    if ((alive >> j) & 1u)
+                                    if (j != k && ((alive >> j) & 1u))
                                         s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
                             }
                             Sden[p] = s_new;
                         }
                     }
+                }
+
+                // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
+                const R lg2G = fast_log2(G);
+                double lsum[1] = {0.0};
+    #pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    R den;
+                    if constexpr (STORE_E) {
+                        den = resum(e[p]);
+                    } else {
+                        den = R(0);
+                        for (int j = 0; j < Kslots; ++j)
+                            if ((alive >> j) & 1u)
+                                den += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                    }
+                    const R lg = fast_log2(den);
+                    ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
+                    lsum[0] += (double)a[p] * (double)ref[p];
+                    if constexpr (STORE_E) {
+                        const R inv = fast_rcp(den);
+                        e[p] *= inv;  // unused slots hold 0
+                        Sden[p] = resum(e[p]);
+                    } else {
+                        Sden[p] = R(1);
+                    }
+                }
+                block_sum<2>(lsum, red_d, par_d, nwaves);
+                // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
+                if (lane < Kslots && ((alive >> lane) & 1u)) {
+                    comp[lane].u = comp[lane].u * m_rcp(G);
+                    comp[lane].c2 = comp[lane].c2 - lg2G;
+                }
+                R Gn = R(0);
+                double pen = 0.0;
+                for (int j = 0; j < Kslots; ++j)
+                    if ((alive >> j) & 1u) Gn += comp[j].u;
+                for (int j = 0; j < Kslots; ++j)
+                    if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
+                G = Gn;
+                const double dpar = K * T + K - 1;
+                // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
+                L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
+
+                // ---- compaction of dead slots (rare) ----
+                if (annihilated) {
+                    for (int k = Kslots - 1; k >= 0; --k) {
+                        if ((alive >> k) & 1u) continue;
+                        if (lane == 0)
+                            for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
+                        if constexpr (STORE_E) {
+    #pragma unroll
+                            for (int j = 0; j + 1 < KMAX; ++j)
+                                if (j >= k) {
+    #pragma unroll
+                                    for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
+                                }
+    #pragma unroll
+                            for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
+                        }
+                        const uint32_t low = alive & ((1u << k) - 1u);
+                        const uint32_t high = (alive >> (k + 1)) << k;
+                        alive = low | high;
+                        --Kslots;
+                    }
+                }
+
+                if (fixed > 0) {
+                    if (s == fixed) break;
+                    L_prev = L_s;
                     continue;
                 }
-                // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
-                CompState<R, D> cn;
-                const R invN = m_rcp(Nk);
-                R dl[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    dl[i] = sums[1 + i] * invN;
-                    cn.mu[i] = ckmu[i] + dl[i];
+                if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
+                if (s == max_sweeps) {
+                    status |= GM_ST_MAXSWEEPS;
+                    break;
                 }
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int j = i; j < D; ++j)
-                        cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
-                const R wk = NkT * m_rcp((R)(N - halfT * K));
-                const R unew = wk * G;
-                G = G - cku + unew;
-                cn.u = unew;
-                if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
-                if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
-                if constexpr (STORE_E) {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
-                        const R s_old = Sden[p];
-                        const R s_new = s_old - e[p][k] + enew;
-                        e[p][k] = enew;
-                        Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
-                    }
-                } else {
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
-                        const R s_old = Sden[p];
-                        R s_new = s_old - eold[p] + enew;
-                        if (!(s_new > R(1e-4) * s_old)) {
-                            // the particle lost most of its density: re-sum exactly
-                            s_new = enew;
-                            for (int j = 0; j < Kslots; ++j)
-                                if (j != k && ((alive >> j) & 1u))
-                                    s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
-                        }
-                        Sden[p] = s_new;
-                    }
-                }
-            }
-
-            // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
-            const R lg2G = fast_log2(G);
-            double lsum[1] = {0.0};
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                R den;
-                if constexpr (STORE_E) {
-                    den = resum(e[p]);
-                } else {
-                    den = R(0);
-                    for (int j = 0; j < Kslots; ++j)
-                        if ((alive >> j) & 1u)
-                            den += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
-                }
-                const R lg = fast_log2(den);
-                ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
-                lsum[0] += (double)a[p] * (double)ref[p];
-                if constexpr (STORE_E) {
-                    const R inv = fast_rcp(den);
-                    e[p] *= inv;  // unused slots hold 0
-                    Sden[p] = resum(e[p]);
-                } else {
-                    Sden[p] = R(1);
-                }
-            }
-            block_sum<2>(lsum, red_d, par_d, nwaves);
-            // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
-            if (lane < Kslots && ((alive >> lane) & 1u)) {
-                comp[lane].u = comp[lane].u * m_rcp(G);
-                comp[lane].c2 = comp[lane].c2 - lg2G;
-            }
-            R Gn = R(0);
-            double pen = 0.0;
-            for (int j = 0; j < Kslots; ++j)
-                if ((alive >> j) & 1u) Gn += comp[j].u;
-            for (int j = 0; j < Kslots; ++j)
-                if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
-            G = Gn;
-            const double dpar = K * T + K - 1;
-            // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
-            L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
-
-            // ---- compaction of dead slots (rare) ----
-            if (annihilated) {
-                for (int k = Kslots - 1; k >= 0; --k) {
-                    if ((alive >> k) & 1u) continue;
-                    if (lane == 0)
-                        for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
-                    if constexpr (STORE_E) {
-#pragma unroll
-                        for (int j = 0; j + 1 < KMAX; ++j)
-                            if (j >= k) {
-#pragma unroll
-                                for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
-                            }
-#pragma unroll
-                        for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
-                    }
-                    const uint32_t low = alive & ((1u << k) - 1u);
-                    const uint32_t high = (alive >> (k + 1)) << k;
-                    alive = low | high;
-                    --Kslots;
-                }
-            }
-
-            if (fixed > 0) {
-                if (s == fixed) break;
                 L_prev = L_s;
-                continue;
             }
-            if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
-            if (s == max_sweeps) {
-                status |= GM_ST_MAXSWEEPS;
-                break;
-            }
-            L_prev = L_s;
+            if (s > cap_sweeps) s = cap_sweeps;
+            if (!warm || fixed > 0 || L_s >= L_one - 1e-5 * fabs(L_one)) break;
+            // rejected warm start: cold start, flags of the cold fit only
+            warm = false;
+            status = GM_ST_WARM_FALLBACK;
+            __syncthreads();
         }
-        if (s > cap_sweeps) s = cap_sweeps;
 
         // ---------------- penalised state into the output record -------------
         // (centred coordinates; k_finish turns it into the final mixture)

@@ -67,13 +67,22 @@ def _sample_cells(rng, counts, D, kmax_true_lo, kmax_true_hi, aniso, vth_lo=0.02
     cum = np.cumsum(frac, axis=1)
     cum[:, -1] = 1.0
     u = rng.random(n_tot)
-    comp = np.empty(n_tot, dtype=np.int64)
-    # per-particle inverse CDF over its cell's fractions
-    cp = cum[cell_of]
-    comp = np.minimum((u[:, None] >= cp).sum(axis=1), ktrue[cell_of] - 1)
+    # per-particle inverse CDF over its cell's fractions (column by column,
+    # without an n_tot x K temporary)
+    comp = np.zeros(n_tot, dtype=np.int64)
+    for k in range(kk):
+        comp += u >= cum[cell_of, k]
+    comp = np.minimum(comp, ktrue[cell_of] - 1)
     z = rng.standard_normal(size=(n_tot, D))
-    Lp = chol[cell_of, comp]
-    v = drift[cell_of, comp] + np.einsum("pij,pj->pi", Lp, z)
+    flat = cell_of * kk + comp
+    dr = drift.reshape(n_cells * kk, D)
+    Lf = chol.reshape(n_cells * kk, D, D)
+    v = np.empty((n_tot, D))
+    for i in range(D):
+        acc = dr[flat, i].copy()
+        for j in range(i + 1):
+            acc += Lf[flat, i, j] * z[:, j]
+        v[:, i] = acc
     truth = {"K": ktrue, "omega": frac, "mu": drift, "sigma": cov, "label": comp}
     return v, truth
 
@@ -162,3 +171,29 @@ def concat_cells(parts):
         counts.append(np.diff(p["cell_off"]))
     counts = np.concatenate(counts)
     return dict(v=np.concatenate(vs), alpha=np.concatenate(al), cell_off=_offsets(counts))
+
+
+def split_start_cells(seed, n_cells=8, n=1000, kmax=16, shift=0.8):
+    """Single isotropic Gaussian 3V cells and a deliberately poor
+    two-component starting mixture per cell that has the generating mean and
+    covariance: components at the generating mean +- shift * vth along x,
+    covariance vth^2 diag(1 - shift^2, 1, 1), weights 1/2.
+    Returns (data, init) with init in the gm_init layout (kmax slots)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = np.full(n_cells, n, dtype=np.int64)
+    v, truth = _sample_cells(rng, counts, 3, 1, 1, aniso=False)
+    alpha = np.ones(len(v))
+    K = np.full(n_cells, 2, np.int32)
+    w = np.zeros((n_cells, kmax))
+    mu = np.zeros((n_cells, kmax, 3))
+    S = np.zeros((n_cells, kmax, 6))
+    for c in range(n_cells):
+        m0 = truth["mu"][c, 0]
+        t = truth["sigma"][c, 0][0, 0]
+        for k, sgn in enumerate((-1.0, 1.0)):
+            w[c, k] = 0.5
+            mu[c, k] = m0
+            mu[c, k, 0] += sgn * shift * np.sqrt(t)
+            S[c, k] = [t * (1.0 - shift * shift), 0.0, 0.0, t, 0.0, t]
+    data = dict(v=v, alpha=alpha, cell_off=_offsets(counts), D=3, truth=truth)
+    return data, {"K": K, "omega": w, "mu": mu, "sigma": S}

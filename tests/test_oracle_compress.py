@@ -395,3 +395,50 @@ def test_two_stream_finds_two_beams_mostly():
         assert np.all(np.minimum(np.abs(mu - 0.2), np.abs(mu + 0.2)) < 0.12)
         assert w[mu > 0].sum() == pytest.approx(0.5, abs=0.01)
         assert 2 <= K <= 5
+
+
+def test_single_gaussian_likelihood_closed_form():
+    """The warm-start acceptance test compares with the penalised likelihood
+    of the single Gaussian with the cell's moments; with weights normalised
+    to sum N it equals N (-D/2 ln 2 pi - 1/2 ln det C - D/2) - (T/2) ln N
+    (eq. lnL-GM with K = 1, d = T)."""
+    d = synth.random_cells(77, 6, 3, 30, 400, weights="uniform")
+    off = d["cell_off"]
+    for c in range(6):
+        v, a = d["v"][off[c]:off[c + 1]], d["alpha"][off[c]:off[c + 1]]
+        n = len(a)
+        W = a.sum()
+        m = (a[:, None] * v).sum(0) / W
+        C = ((a[:, None, None] * (v - m)[:, :, None] * (v - m)[:, None, :]).sum(0)) / W
+        iu = np.triu_indices(3)
+        L = oracle.penalised_L(v, a, np.array([1.0]), m[None], C[iu][None])
+        closed = n * (-1.5 * np.log(2 * np.pi) - 0.5 * np.log(np.linalg.det(C)) - 1.5) - 4.5 * np.log(n)
+        assert L == pytest.approx(closed, rel=1e-12)
+
+
+def test_poor_warm_start_falls_back_to_cold():
+    """A two-component start on single-Gaussian data, stopped after a few
+    sweeps while both halves still hold ~n/2 particles, scores below the
+    single Gaussian (the split buys little likelihood and costs the
+    penalty of 10 more parameters and two weights): every cell is refitted
+    from the cold start, with the same result as a cold run and the flag
+    set.  The generating Gaussian as start is kept."""
+    d, init = synth.split_start_cells(91, n_cells=6, n=1000, kmax=16)
+    S = oracle.STATUS
+    warm = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=16, seed=5, init=init, max_sweeps=5)
+    cold = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=16, seed=5, max_sweeps=5)
+    assert ((warm["status"] & S["WARM_FALLBACK"]) != 0).all(), (warm["K"], warm["L_pen"], warm["status"])
+    for k in ("K", "omega", "mu", "sigma", "L_pen", "L_final", "sweeps"):
+        np.testing.assert_array_equal(warm[k], cold[k])
+    np.testing.assert_array_equal(warm["status"], cold["status"] | S["WARM_FALLBACK"])
+    assert (warm["visits"] > cold["visits"]).all()
+    # the generating Gaussian as start: accepted, one component
+    good = {"K": np.ones(6, np.int32), "omega": np.zeros((6, 16)), "mu": np.zeros((6, 16, 3)),
+            "sigma": np.zeros((6, 16, 6))}
+    iu = np.triu_indices(3)
+    good["omega"][:, 0] = 1.0
+    good["mu"][:, 0] = d["truth"]["mu"][:, 0]
+    good["sigma"][:, 0] = d["truth"]["sigma"][:, 0][:, iu[0], iu[1]]
+    r = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=16, seed=5, init=good)
+    assert ((r["status"] & S["WARM_FALLBACK"]) == 0).all()
+    assert (r["K"] == 1).all()

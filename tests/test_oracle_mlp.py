@@ -133,3 +133,15 @@ def test_targets_decode_round_trip():
             assert dec["omega"][c, q] == pytest.approx(mix["omega"][c, k] / wsum, rel=1e-12)
             np.testing.assert_allclose(dec["mu"][c, q], mix["mu"][c, k], rtol=1e-10, atol=1e-12)
             np.testing.assert_allclose(dec["sigma"][c, q], mix["sigma"][c, k], rtol=1e-8, atol=1e-14)
+
+
+def test_decode_without_frame_keeps_cold_start():
+    """Cells with no whitening frame (empty, singular covariance) decode to
+    K = 0 with zero slots, so compress starts them cold."""
+    Y = np.random.default_rng(1).normal(size=(3, 160))
+    fr = np.zeros((3, 9))
+    fr[0, :3] = 0.2
+    off = np.array([0, 0, 7, 8], np.int64)
+    dec = oracle.warm_decode(Y, fr, off, 16)
+    assert (dec["K"] == 0).all()
+    assert not dec["omega"].any() and not dec["mu"].any() and not dec["sigma"].any()
