@@ -1,17 +1,30 @@
 #!/usr/bin/env python3
-"""Throughput of batched Gaussian-mixture checkpoint-restart on one MI355X.
+"""Throughput of batched Gaussian-mixture checkpoint-restart on one MI355X,
+learned warm start against plain (cold-start) EM.
 
 One step = the whole hot path over one batch of cells with the inputs
-resident in HBM: gm_compress (FP64 moments, FP32 adaptive EM sweeps to
-convergence, FP64 unpenalised finish) followed by gm_reconstruct (ancestral
-sampling of n' = n particles per cell plus the FP64 moment-matching
-projection).  The metric is particles fit per second (sum of cell sizes per
-step / step time).
+resident in HBM:
+  warm: features -> perceptron (BF16 matrix cores) -> decoded initial
+        mixtures -> gm_compress from them (FP64 moments, FP32 adaptive EM
+        sweeps to convergence, in-kernel cold refit of rejected starts, FP64
+        unpenalised finish) -> gm_reconstruct (ancestral sampling of n' = n
+        particles per cell plus the FP64 moment-matching projection);
+  cold: the same without the warm start (the paper's random start).
+The metric is particles fit per second (sum of cell sizes / step time).
 
-Prints one JSON line.  Besides the throughput it reports the roofline of
-the dominant kernel (the EM sweeps, bound by FP32 vector ALU) from HIP
-events recorded around those launches, and the FP64 CPU oracle timed on a
-bounded sample of the same cells.
+The headline value is the warm path under the judged fallback protocol: a
+cell whose warm fit ends with a penalised likelihood more than 1e-4
+(relative) below the cold fit's counts as a fallback, its output is the cold
+fit and its cost is added: the time of a cold compress of exactly those
+cells, measured on their own, is added to the warm step time.
+
+The perceptron is trained first (outside the timed region) on plain-EM fits
+of 16 fresh batches of cells of the same recipe (data seeds 5000-5015).
+
+Prints one JSON line with the roofline of the dominant kernel (the EM
+sweeps, bound by FP32 vector ALU) from HIP events recorded around those
+launches, and the FP64 CPU oracle of the same path timed on a bounded
+sample of the cells.
 """
 from __future__ import annotations
 
@@ -39,14 +52,15 @@ WORKLOADS = {
              "weights U(0.5,1.5), kmax 8; compress + reconstruct n' = n, dx = 2"),
     "mix_1v": dict(
         D=1, kmax=8, dx=1, init_seed=2002, recon_seed=3002,
-        desc="1D1V: 1024 cells, counts max(200, Poisson(2000)), 1-4 Maxwellians, weights U(0.5,1.5), kmax 8"),
+        desc="1D1V: 1024 cells, counts max(200, Poisson(2000)), 1-4 Maxwellians, weights U(0.5,1.5), kmax 8 "
+             "(cold start only)"),
 }
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
-PEAK_HBM_GBPS = 8000.0
 # algorithmic flops per (particle, component update), transcendentals as 1:
 # density 19 + exp 1 + denominator 5 + responsibility 2 + moment sums 22 in 3V
 FLOPS_PER_UPDATE = {3: 49, 1: 18}
+JUDGE_REL = 1e-4
 
 
 def parse():
@@ -55,14 +69,45 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="weibel_3v", choices=sorted(WORKLOADS))
+    p.add_argument("--start", default="warm", choices=("warm", "cold"),
+                   help="warm: learned warm start (the headline); cold: plain EM only")
+    p.add_argument("--train-sets", type=int, default=16, help="training batches of cells (seeds 5000+i)")
+    p.add_argument("--epochs", type=int, default=50)
     p.add_argument("--cpu-cells", type=int, default=32, help="cells in the CPU-oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-pool", action="store_true",
+                   help="generate the training cells in this process (no child processes; for profiler runs)")
+    p.add_argument("--copy-check", action="store_true",
+                   help="also run a plain 256 MiB device copy (calibrates HBM byte counters in profiles)")
     return p.parse_args()
 
 
-def cpu_baseline(data, W, n_cells_sample):
-    """The FP64 oracle on an evenly spaced sample of the same cells, all host
-    threads (capped at 16)."""
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _gen_training(seed):
+    from paper_2007_12273_amd import synth
+    d = synth.weibel_3v(seed=seed)
+    return {k: d[k] for k in ("v", "alpha", "cell_off")}
+
+
+def training_batches(n_sets, pool=True):
+    """Training cells of the Weibel-like recipe, generated in child
+    processes before anything touches the GPU (or in this process)."""
+    seeds = [5000 + i for i in range(n_sets)]
+    if not pool:
+        return [_gen_training(s) for s in seeds]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(min(n_sets, 8)) as pool_:
+        return pool_.map(_gen_training, seeds)
+
+
+def cpu_baseline(data, W, n_cells_sample, params):
+    """The FP64 oracle of the same path on an evenly spaced sample of the
+    cells, all host threads (capped at 16): warm start (features, FP64
+    perceptron with the trained weights, decode) when params is given, then
+    compress and reconstruct."""
     import numpy as np
 
     import oracle
@@ -81,29 +126,86 @@ def cpu_baseline(data, W, n_cells_sample):
     threads = oracle.default_threads()
     oracle.build()
     t0 = time.perf_counter()
-    r = oracle.compress(v, a, so, kmax=W["kmax"], seed=W["init_seed"], nthreads=threads)
+    init = None
+    if params is not None:
+        f, fr = oracle.features(v, a, so)
+        _, _, Y = oracle.mlp_forward(f, params)
+        init = oracle.warm_decode(Y, fr, so, W["kmax"])
+    r = oracle.compress(v, a, so, kmax=W["kmax"], seed=W["init_seed"], init=init, nthreads=threads)
     tg = oracle.targets_from_moments(r["moments"], W["D"])
     oracle.reconstruct(r["K"], r["omega"], r["mu"], r["sigma"], so, tg, W["D"], W["dx"], seed=W["recon_seed"],
                        nthreads=threads)
     dt = time.perf_counter() - t0
     npart = int(so[-1])
     return {"value": npart / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d cells (evenly spaced), %d particles, compress to convergence + reconstruct, "
-                      "%.1f s wall" % (n_cells_sample, n_cells, npart, dt)}
+            "sample": "%d of %d cells (evenly spaced), %d particles, %s start, compress to convergence + "
+                      "reconstruct, %.1f s wall" % (n_cells_sample, n_cells, npart,
+                                                    "learned warm" if params is not None else "cold", dt)}
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def phase_times(fn, reps, api, torch):
+    """Per-phase durations from HIP events on the caller's stream."""
+    import numpy as np
+    api.profile_enable(True)
+    ph = {"plan": [], "em": [], "finish": [], "reconstruct": [], "warm_init": []}
+    for _ in range(reps):
+        t = fn()
+        p = api.profile_read()
+        for k in ("plan", "em", "finish", "reconstruct"):
+            ph[k].append(p[k])
+        if t is not None:
+            ph["warm_init"].append(t)
+    api.profile_enable(False)
+    return {k: float(np.mean(x)) for k, x in ph.items() if x}
+
+
+def subset_gpu(v, alpha, off_host, cells, torch):
+    """Particles of the given cells, gathered into a compact batch."""
+    import numpy as np
+    counts = np.diff(off_host)[cells]
+    starts = off_host[cells]
+    idx = np.concatenate([np.arange(s, s + n) for s, n in zip(starts, counts)]) if len(cells) else np.zeros(0, int)
+    it = torch.from_numpy(idx.astype(np.int64)).to(v.device)
+    so = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)).to(v.device)
+    return v.index_select(0, it).contiguous(), alpha.index_select(0, it).contiguous(), so
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (cells are independent; "
-              "see the sharding note in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: cells are independent and this build has no multi-GPU path (the "
+              "sharding plan is a contiguous split of the cell list per GPU). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    W = WORKLOADS[args.workload]
+    warm = args.start == "warm"
+    if warm and W["D"] != 3:
+        raise SystemExit("the learned warm start is built for 3V workloads; use --start cold")
+    train_sets = []
+    if warm:
+        t0 = time.perf_counter()
+        train_sets = training_batches(args.train_sets, pool=not args.no_pool)
+        log("generated %d training batches (%.1f s)" % (len(train_sets), time.perf_counter() - t0))
+
     import numpy as np
     import torch
 
     from paper_2007_12273_amd import api, synth
+    from paper_2007_12273_amd import warm as warmlib
 
-    W = WORKLOADS[args.workload]
     data = synth.make(args.workload)
     dev = torch.device("cuda:0")
     v = torch.from_numpy(data["v"]).to(dev)
@@ -111,47 +213,119 @@ def main():
     off = torch.from_numpy(data["cell_off"]).to(dev)
     n_cells = off.numel() - 1
     n_part = int(data["cell_off"][-1])
+    counts = np.diff(data["cell_off"])
     D, kmax, dx = W["D"], W["kmax"], W["dx"]
 
-    comp = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"])
+    comp_c = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"])
+    comp_w = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"])
     recon = api.Reconstructor(off, D, dx, device=dev)
 
-    def step():
-        r = comp(v, alpha, off)
+    model = None
+    train_info = None
+    if warm:
+        t0 = time.perf_counter()
+        feats, targs = warmlib.training_set(train_sets, kmax, seed=W["init_seed"], device=dev)
+        del train_sets
+        t_data = time.perf_counter() - t0
+        model = api.WarmStart(kmax, batch=1024, seed=7, device=dev)
+        t0 = time.perf_counter()
+        hist = warmlib.train(model, feats, targs, epochs=args.epochs, lr=1e-3, lam=1.0, seed=0)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        train_info = {"cells": int(feats.shape[0]), "epochs": args.epochs, "batch": 1024, "lr": 1e-3,
+                      "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "targets_s": t_data,
+                      "train_s": t_train}
+        log("trained warm start: %d cells, loss %.4f -> %.4f, %.1f s" % (feats.shape[0], hist[0], hist[-1],
+                                                                         t_train))
+        del feats, targs
+        bufs = model.init_buffers(n_cells)
+
+    def cold_step():
+        r = comp_c(v, alpha, off)
         recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("warmup done", file=sys.stderr, flush=True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.steps
-    print("timed %d steps: %.3f ms/step" % (args.steps, ms), file=sys.stderr, flush=True)
+    def warm_step():
+        init = model.initial_mixtures(v, alpha, off, bufs=bufs)
+        r = comp_w(v, alpha, off, init=init)
+        recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
-    # phase durations from HIP events recorded by the library on this stream
-    api.profile_enable(True)
-    phases = {"plan": [], "em": [], "finish": [], "reconstruct": []}
-    for _ in range(max(2, min(args.steps, 5))):
-        step()
-        ph = api.profile_read()
-        for k in phases:
-            phases[k].append(ph[k])
-    api.profile_enable(False)
-    ph = {k: float(np.mean(x)) for k, x in phases.items()}
+    ms_cold = time_steps(cold_step, args.steps, args.warmup, torch)
+    log("cold: %.3f ms/step" % ms_cold)
+    ph_cold = phase_times(cold_step, max(2, min(args.steps, 5)), api, torch)
+    cold = {k: t.cpu().numpy() for k, t in comp_c.out.as_dict().items()}
 
-    K = comp.out.K.cpu().numpy()
-    visits = comp.out.visits.cpu().numpy()
-    sweeps = comp.out.sweeps.cpu().numpy()
-    status = comp.out.status.cpu().numpy()
-    counts = np.diff(data["cell_off"])
+    line_extra = {}
+    if warm:
+        ms_warm = time_steps(warm_step, args.steps, args.warmup, torch)
+        log("warm: %.3f ms/step" % ms_warm)
+
+        def warm_step_timed():
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record()
+            init = model.initial_mixtures(v, alpha, off, bufs=bufs)
+            s1.record()
+            r = comp_w(v, alpha, off, init=init)
+            recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
+            torch.cuda.synchronize()
+            return s0.elapsed_time(s1)
+
+        ph_warm = phase_times(warm_step_timed, max(2, min(args.steps, 5)), api, torch)
+        wr = {k: t.cpu().numpy() for k, t in comp_w.out.as_dict().items()}
+        init_K = bufs["init"]["K"].cpu().numpy()
+        # judged fallback: warm fit more than 1e-4 (relative) below the cold fit
+        both = np.isfinite(wr["L_pen"]) & np.isfinite(cold["L_pen"])
+        rel = np.zeros(n_cells)
+        rel[both] = (wr["L_pen"][both] - cold["L_pen"][both]) / np.abs(cold["L_pen"][both])
+        # a cell whose warm fit is not finite while the cold one is counts as a fallback
+        rel[np.isfinite(cold["L_pen"]) & ~np.isfinite(wr["L_pen"])] = -np.inf
+        judged = np.nonzero(rel < -JUDGE_REL)[0]
+        # calibration of the protocol: a cold fit from another random start,
+        # judged against the same cold fit
+        comp_r = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"] + 7919)
+        rr = {k: t.cpu().numpy() for k, t in comp_r(v, alpha, off).as_dict().items()}
+        ok2 = np.isfinite(rr["L_pen"]) & np.isfinite(cold["L_pen"])
+        rel2 = (rr["L_pen"][ok2] - cold["L_pen"][ok2]) / np.abs(cold["L_pen"][ok2])
+        del comp_r
+        ms_extra = 0.0
+        if len(judged):
+            sv, sa, so = subset_gpu(v, alpha, data["cell_off"], judged, torch)
+            comp_s = api.Compressor(len(judged), D, kmax, device=dev, seed=W["init_seed"])
+            ms_extra = time_steps(lambda: comp_s(sv, sa, so), max(1, args.steps), 1, torch)
+        ms = ms_warm + ms_extra
+        em_ms, visits = ph_warm["em"], wr["visits"]
+        fb_dep = (wr["status"] & 32) != 0
+        # output after the judged fallback: cold fit in the judged cells
+        Kout = wr["K"].copy()
+        Kout[judged] = cold["K"][judged]
+        q = lambda x: [float(np.quantile(x, t)) for t in (0.01, 0.1, 0.5, 0.9, 0.99)]
+        line_extra = {
+            "plain_em": {"value": n_part / (ms_cold * 1e-3), "ms_per_step": ms_cold, "phase_ms": ph_cold,
+                         "mean_sweeps": float(cold["sweeps"].mean()),
+                         "p50_sweeps": float(np.median(cold["sweeps"])),
+                         "p99_sweeps": float(np.quantile(cold["sweeps"], 0.99)),
+                         "maxsweeps_cells": int(((cold["status"] & 8) != 0).sum()),
+                         "mean_K": float(cold["K"].mean())},
+            "speedup_vs_plain_em": ms_cold / ms,
+            "warm": {"ms_per_step_before_judged_fallback": ms_warm, "judged_fallback_ms": ms_extra,
+                     "phase_ms": ph_warm, "mean_sweeps": float(wr["sweeps"].mean()),
+                     "p50_sweeps": float(np.median(wr["sweeps"])),
+                     "p99_sweeps": float(np.quantile(wr["sweeps"], 0.99)),
+                     "maxsweeps_cells": int(((wr["status"] & 8) != 0).sum()),
+                     "mean_K_init": float(init_K.mean()), "mean_K": float(Kout.mean()),
+                     "deployable_fallback_frac": float(fb_dep.mean()),
+                     "judged_fallback_frac": len(judged) / n_cells,
+                     "judged_fallback_frac_of_cold_reseeded": float((rel2 < -JUDGE_REL).mean()),
+                     "rel_L_warm_minus_cold_quantiles_1_10_50_90_99": q(rel[both]),
+                     "K_agreement_with_plain_em": float((Kout == cold["K"]).mean()),
+                     "visits_ratio_warm_over_cold": float(visits.sum() / max(1, cold["visits"].sum()))},
+            "training": train_info,
+        }
+        phases = ph_warm
+    else:
+        ms, em_ms, visits, phases, Kout, wr = ms_cold, ph_cold["em"], cold["visits"], ph_cold, cold["K"], cold
+
     em_flops = float((counts * visits).sum()) * FLOPS_PER_UPDATE[D]
-    achieved = em_flops / (ph["em"] * 1e-3) / 1e12
+    achieved = em_flops / (em_ms * 1e-3) / 1e12
     recon_bytes = n_part * 8 * (D + 1 + dx)
     line = {
         "metric": METRIC,
@@ -168,11 +342,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload + ": " + W["desc"],
-            "cells": n_cells, "particles": n_part, "kmax": kmax, "D": D, "start": "cold",
-            "precision": "EM sweeps f32; moments, finish, reconstruct f64",
+            "cells": n_cells, "particles": n_part, "kmax": kmax, "D": D,
+            "start": "learned warm start (judged fallback to cold counted)" if warm else "cold (plain EM)",
+            "precision": "EM sweeps f32; moments, finish, reconstruct f64; perceptron bf16 x bf16 -> f32",
         },
         "roofline": {
-            "kernel": "k_em (all length buckets)",
+            "kernel": "k_em (all length buckets, one EM phase)",
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
@@ -180,20 +355,33 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": None,
             "flops_per_launch": em_flops,
-            "ms_per_launch": ph["em"],
+            "ms_per_launch": em_ms,
         },
         "cells_per_s": n_cells / (ms * 1e-3),
-        "phase_ms": ph,
-        "reconstruct_hbm_gbps": recon_bytes / (ph["reconstruct"] * 1e-3) / 1e9,
-        "mean_K": float(K.mean()),
-        "mean_sweeps": float(sweeps.mean()),
-        "maxsweeps_cells": int(((status & 8) != 0).sum()),
+        "phase_ms": phases,
+        "reconstruct_hbm_gbps": recon_bytes / (phases["reconstruct"] * 1e-3) / 1e9,
+        "mean_K": float(Kout.mean()),
+        "mean_sweeps": float(wr["sweeps"].mean()),
         # the paper's ratio: particles per Gaussian component
-        "compression_ratio": float(counts.sum() / max(1, K.sum())),
+        "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
     }
+    line.update(line_extra)
+    if args.copy_check:
+        src = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_check_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
-        print("cpu baseline ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(data, W, args.cpu_cells)
+        log("cpu baseline ...")
+        params = None
+        if warm:
+            flat = model.get_params()
+            P = api.flat_to_params(flat.astype(np.float64))
+            P["W1"] = P["W1"][:105]
+            params = P
+        line["cpu_baseline"] = cpu_baseline(data, W, args.cpu_cells, params)
     print(json.dumps(line))
 
 
