@@ -593,6 +593,7 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
                 L_prev = L_s;
                 continue;
             }
+            if (!isfinite(L_s)) break; /* eq. (lnL-GM) undefined: no further sweep can help */
             if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
             if (s == J->max_sweeps) {
                 status |= ORC_MAXSWEEPS;

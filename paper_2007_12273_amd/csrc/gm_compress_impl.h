@@ -355,6 +355,62 @@ __device__ __forceinline__ R log2_term(const CompState<R, D>& cs, const R (&x)[D
 
 constexpr int kEmMaxWaves = kEmMaxThreads / 64;
 
+template <int CTRL, int ROW_MASK = 0xf, typename T>
+__device__ __forceinline__ T dpp_get(T x)
+{
+    if constexpr (std::is_same<T, float>::value)
+        return __int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(x)));
+    else
+        return dpp_d<CTRL, ROW_MASK>(x);
+}
+
+// Workgroup sum of the NV M-step sums of one component update, delivered to
+// every thread.  The 64-lane tree of wave_sum is applied to all NV values one
+// level at a time, so the independent DPP operations fill each other's wait
+// states.  Lane 0 of every wave publishes its wave's sums; after one barrier
+// lane v < NV adds value v over all MAXW slots in wave order: slots of absent
+// waves hold zeros (the buffer is cleared when the kernel starts and only
+// present waves write), so no per-wave test is needed.  The additions happen
+// in the same order as in block_sum.
+template <int NVMAX, int MAXW, typename T, int NV>
+__device__ __forceinline__ void em_block_sum(T (&x)[NV], T* buf, int& parity, int nwaves)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0xB1>(x[v]);   // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x4E>(x[v]);   // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x141>(x[v]);  // row_half_mirror
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x140>(x[v]);  // row_mirror
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142, 0xa>(x[v]);  // row_bcast:15
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143, 0xc>(x[v]);  // row_bcast:31
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);
+    if (nwaves == 1) return;
+    T* b = buf + parity * (MAXW * NVMAX);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) b[wid * NVMAX + v] = x[v];
+    }
+    __syncthreads();
+    T t = T(0);
+    if (lane < NV) {
+        T part[MAXW];
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) part[w] = b[w * NVMAX + lane];
+        t = part[0];
+#pragma unroll
+        for (int w = 1; w < MAXW; ++w) t += part[w];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = lane_bcast(t, v);
+    parity ^= 1;
+}
+
 // sum of all slots of a density-term vector (unused and dead slots hold 0)
 template <typename V>
 __device__ __forceinline__ auto resum(const V& v) -> decltype(v[0] + v[0])
@@ -400,11 +456,12 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
     __shared__ CompressArgs A;   // arguments read where they are used, not pinned in SGPRs
     __shared__ CompState<R, D> compw[kEmMaxWaves][KMAX];
     __shared__ double red_d[2 * kMaxWaves * 2];
-    __shared__ R red_r[2 * kMaxWaves * NS];
+    __shared__ R red_r[2 * kEmMaxWaves * NS];  // zero where no wave writes (em_block_sum)
     __shared__ int s_idx;
     __shared__ int s_flag;
 
     if (tid == 0) A = A_in;
+    for (int t = tid; t < 2 * kEmMaxWaves * NS; t += blockDim.x) red_r[t] = R(0);
     __syncthreads();
     const int nwaves = A.nwaves;
     const int bucket = A.bucket;
@@ -495,16 +552,16 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     double wsum = 0.0;
                     for (int j = 0; j < K; ++j) wsum += A.init.omega[s0 + j];
                     const size_t sk = s0 + tid;
-    #pragma unroll
+#pragma unroll
                     for (int d = 0; d < D; ++d) cs.mu[d] = (R)(A.init.mu[sk * D + d] - ci->m[d]);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < NT; ++q) cs.S[q] = (R)A.init.sigma[sk * NT + q];
                     cs.u = (R)(A.init.omega[sk] / wsum);
                 } else {
                     const int ip = A.init_idx[(size_t)c * kInitSlots + tid];
-    #pragma unroll
+#pragma unroll
                     for (int d = 0; d < D; ++d) cs.mu[d] = (R)(vc[(size_t)ip * D + d] - ci->m[d]);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < NT; ++q) cs.S[q] = (R)ci->C[q];
                     cs.u = (R)(1.0 / K);
                 }
@@ -520,22 +577,22 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
             if constexpr (STORE_E) {
                 for (int j = 0; j < K; ++j) {
                     const CompState<R, D> cj = comp[j];
-    #pragma unroll
+#pragma unroll
                     for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
                 }
-    #pragma unroll
+#pragma unroll
                 for (int p = 0; p < P; ++p) {
                     R mx = e[p][0];
-    #pragma unroll
+#pragma unroll
                     for (int j = 1; j < KMAX; ++j)
                         if (j < K) mx = fmax(mx, e[p][j]);
                     ref[p] = mx;
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
                     Sden[p] = resum(e[p]);
                 }
             } else {
-    #pragma unroll
+#pragma unroll
                 for (int p = 0; p < P; ++p) {
                     R mx = R(-1e30);
                     for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
@@ -552,6 +609,60 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
             const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
             int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
             uint32_t alive = (1u << K) - 1u;
+            // A particle whose density sum falls far below its reference (every
+            // live component now far from it, e.g. after the one that covered
+            // it was annihilated or moved away) gets its terms recomputed in
+            // log2 space about their own maximum, as a log-sum-exp would, so
+            // that no term underflows to zero.
+            const R rebase_below = R(9.094947017729282e-13);  // 2^-40
+            auto rebase_store = [&](VecK& ep, const R (&xp)[D], R& refp) -> R {
+                R mx = R(-INFINITY);
+#pragma unroll
+                for (int j = 0; j < KMAX; ++j) {
+                    const bool live = j < Kslots && ((alive >> j) & 1u);
+                    const R t = live ? log2_term<R, D>(comp[j], xp) : R(-INFINITY);
+                    ep[j] = t;
+                    mx = fmax(mx, t);
+                }
+                if (!(mx > R(-INFINITY))) return R(0);
+#pragma unroll
+                for (int j = 0; j < KMAX; ++j)
+                    ep[j] = (j < Kslots && ((alive >> j) & 1u)) ? fast_exp2(ep[j] - mx) : R(0);
+                refp = mx;
+                return resum(ep);
+            };
+            auto rebase_sum = [&](const R (&xp)[D], R& refp) -> R {
+                R mx = R(-INFINITY);
+                for (int j = 0; j < Kslots; ++j)
+                    if ((alive >> j) & 1u) mx = fmax(mx, log2_term<R, D>(comp[j], xp));
+                if (!(mx > R(-INFINITY))) return R(0);
+                R sum = R(0);
+                for (int j = 0; j < Kslots; ++j)
+                    if ((alive >> j) & 1u) sum += fast_exp2(log2_term<R, D>(comp[j], xp) - mx);
+                refp = mx;
+                return sum;
+            };
+            // Particles flagged in `low` lost most of their density in an
+            // update (the running sum may have cancelled): re-sum their terms
+            // exactly, and rebase those whose sum is still tiny.  Particles
+            // flagged in `big` got a term more than 2^64 above their reference
+            // (a component moved onto a particle that had been rebased far
+            // down): rebase them.  The branch is wave-uniform and rarely taken.
+            auto repair_store = [&](uint32_t low, uint32_t big) {
+                if constexpr (STORE_E) {
+                    if (__builtin_amdgcn_ballot_w64((low | big) != 0) == 0) return;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if ((big >> p) & 1u) {
+                            Sden[p] = rebase_store(e[p], x[p], ref[p]);
+                        } else if ((low >> p) & 1u) {
+                            Sden[p] = resum(e[p]);
+                            if (!(Sden[p] > rebase_below)) Sden[p] = rebase_store(e[p], x[p], ref[p]);
+                        }
+                    }
+                }
+            };
+
             double L_prev = 0.0;
             for (s = 1; s <= cap_sweeps; ++s) {
                 bool annihilated = false;
@@ -559,42 +670,42 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     if (!((alive >> k) & 1u)) continue;
                     ++visits;
                     R ckmu[D];
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
                     const R cku = comp[k].u;
                     // E-step of k with the current parameters of every component,
                     // and the M-step sums about the current mean of k
                     R sums[NS];
-    #pragma unroll
+#pragma unroll
                     for (int t = 0; t < NS; ++t) sums[t] = R(0);
                     [[maybe_unused]] R eold[STORE_E ? 1 : P];
                     auto accumulate = [&](int p, R ek, R den) {
                         const R inv = den > R(0) ? fast_rcp(den) : R(0);
                         const R g = a[p] * ek * inv;
                         R d[D];
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
                         sums[0] += g;
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < D; ++i) {
                             const R gd = g * d[i];
                             sums[1 + i] += gd;
-    #pragma unroll
+#pragma unroll
                             for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
                         }
                     };
                     if constexpr (STORE_E) {
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
                     } else {
                         const CompState<R, D> ck = comp[k];
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < P; ++p) {
                             eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
                             accumulate(p, eold[p], Sden[p]);
                         }
                     }
-                    block_sum<NS>(sums, red_r, par_r, nwaves);
+                    em_block_sum<NS, kEmMaxWaves>(sums, red_r, par_r, nwaves);
                     const R Nk = sums[0];
                     const R NkT = Nk - (R)halfT;
                     if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
@@ -605,16 +716,18 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                         --K;
                         annihilated = true;
                         if constexpr (STORE_E) {
-    #pragma unroll
+                            uint32_t low = 0;
+#pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const R s_old = Sden[p];
                                 const R s_new = s_old - e[p][k];
                                 e[p][k] = R(0);
-                                // a particle that lost most of its density: re-sum exactly
-                                Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
+                                Sden[p] = s_new;
+                                low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
                             }
+                            repair_store(low, 0u);
                         } else {
-    #pragma unroll
+#pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const R s_old = Sden[p];
                                 R s_new = s_old - eold[p];
@@ -624,7 +737,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                                         if ((alive >> j) & 1u)
                                             s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
                                 }
-                                Sden[p] = s_new;
+                                Sden[p] = (s_new > rebase_below) ? s_new : rebase_sum(x[p], ref[p]);
                             }
                         }
                         continue;
@@ -633,14 +746,14 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     CompState<R, D> cn;
                     const R invN = m_rcp(Nk);
                     R dl[D];
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < D; ++i) {
                         dl[i] = sums[1 + i] * invN;
                         cn.mu[i] = ckmu[i] + dl[i];
                     }
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < D; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int j = i; j < D; ++j)
                             cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
                     const R wk = NkT * m_rcp((R)(N - halfT * K));
@@ -650,18 +763,24 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
                     if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
                     if constexpr (STORE_E) {
-    #pragma unroll
+                        uint32_t low = 0, big = 0;
+#pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
+                            const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
+                            const R enew = fast_exp2(fmin(dt, R(64)));
                             const R s_old = Sden[p];
                             const R s_new = s_old - e[p][k] + enew;
                             e[p][k] = enew;
-                            Sden[p] = (s_new > R(1e-3) * s_old) ? s_new : resum(e[p]);
+                            Sden[p] = s_new;
+                            low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
+                            big |= (uint32_t)(dt > R(64)) << p;
                         }
+                        repair_store(low, big);
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            const R enew = fast_exp2(fmin(log2_term<R, D>(cn, x[p]) - ref[p], R(64)));
+                            const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
+                            const R enew = fast_exp2(fmin(dt, R(64)));
                             const R s_old = Sden[p];
                             R s_new = s_old - eold[p] + enew;
                             if (!(s_new > R(1e-4) * s_old)) {
@@ -671,7 +790,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                                     if (j != k && ((alive >> j) & 1u))
                                         s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
                             }
-                            Sden[p] = s_new;
+                            Sden[p] = (s_new > rebase_below && !(dt > R(64))) ? s_new : rebase_sum(x[p], ref[p]);
                         }
                     }
                 }
@@ -679,7 +798,9 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                 // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
                 const R lg2G = fast_log2(G);
                 double lsum[1] = {0.0};
-    #pragma unroll
+                R dens[P];
+                uint32_t low = 0;
+#pragma unroll
                 for (int p = 0; p < P; ++p) {
                     R den;
                     if constexpr (STORE_E) {
@@ -690,6 +811,23 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                             if ((alive >> j) & 1u)
                                 den += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
                     }
+                    dens[p] = den;
+                    low |= (uint32_t)!(den > rebase_below) << p;
+                }
+                if (__builtin_amdgcn_ballot_w64(low != 0) != 0) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if ((low >> p) & 1u) {
+                            if constexpr (STORE_E)
+                                dens[p] = rebase_store(e[p], x[p], ref[p]);
+                            else
+                                dens[p] = rebase_sum(x[p], ref[p]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const R den = dens[p];
                     const R lg = fast_log2(den);
                     ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
                     lsum[0] += (double)a[p] * (double)ref[p];
@@ -701,7 +839,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                         Sden[p] = R(1);
                     }
                 }
-                block_sum<2>(lsum, red_d, par_d, nwaves);
+                block_sum<2, kEmMaxWaves>(lsum, red_d, par_d, nwaves);
                 // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
                 if (lane < Kslots && ((alive >> lane) & 1u)) {
                     comp[lane].u = comp[lane].u * m_rcp(G);
@@ -725,13 +863,13 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                         if (lane == 0)
                             for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
                         if constexpr (STORE_E) {
-    #pragma unroll
+#pragma unroll
                             for (int j = 0; j + 1 < KMAX; ++j)
                                 if (j >= k) {
-    #pragma unroll
+#pragma unroll
                                     for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
                                 }
-    #pragma unroll
+#pragma unroll
                             for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
                         }
                         const uint32_t low = alive & ((1u << k) - 1u);
@@ -746,6 +884,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     L_prev = L_s;
                     continue;
                 }
+                if (!isfinite(L_s)) break;  // the objective is undefined: no further sweep can help
                 if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
                 if (s == max_sweeps) {
                     status |= GM_ST_MAXSWEEPS;

@@ -100,7 +100,8 @@ __device__ __forceinline__ double wave_sum(double x)
 
 // Workgroup-wide sum of NV values; every thread receives the totals.  Lane
 // 0 of every wave publishes its wave's sums; after one barrier lane v < NV
-// adds the per-wave partials of value v in wave order and the totals are
+// adds the per-wave partials of value v in wave order (MAXW bounds the wave
+// count so the loads can all be issued together) and the totals are
 // broadcast back with readlane.  The order of additions is fixed, so all
 // threads and all runs see identical totals.  `buf` holds two halves of
 // kMaxWaves * NVMAX values (NVMAX >= every NV used with the buffer);
@@ -120,10 +121,11 @@ __device__ __forceinline__ double lane_bcast(double x, int lane)
     return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-template <int NVMAX, typename T, int NV>
+template <int NVMAX, int MAXW = kMaxWaves, typename T, int NV>
 __device__ __forceinline__ void block_sum(T (&x)[NV], T* buf, int& parity, int nwaves)
 {
     static_assert(NV <= NVMAX && NVMAX <= 64, "reduction buffer too small");
+    static_assert(MAXW <= kMaxWaves, "more waves than the buffer holds");
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = wave_sum(x[v]);
     if (nwaves == 1) return;
@@ -136,8 +138,15 @@ __device__ __forceinline__ void block_sum(T (&x)[NV], T* buf, int& parity, int n
     __syncthreads();
     T t = T(0);
     if (lane < NV) {
-        t = b[lane];
-        for (int w = 1; w < nwaves; ++w) t += b[w * NVMAX + lane];
+        // all MAXW partials are loaded at once (slots of absent waves are in
+        // the buffer and discarded), then added in wave order
+        T part[MAXW];
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) part[w] = b[w * NVMAX + lane];
+        t = part[0];
+#pragma unroll
+        for (int w = 1; w < MAXW; ++w)
+            if (w < nwaves) t += part[w];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = lane_bcast(t, v);

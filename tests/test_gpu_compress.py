@@ -81,6 +81,10 @@ def _check_record(g, o, D, par_tol=1e-4, L_tol=1e-4, k_frac=1.0, cells=None, par
         errs.append(max(mixture_errors(g, o, c, D)))
         eL = abs(g["L_pen"][c] - o["L_pen"][c]) / abs(o["L_pen"][c])
         eF = abs(g["L_final"][c] - o["L_final"][c]) / abs(o["L_final"][c])
+        if max(eL, eF) >= L_tol:
+            print("%s: cell %d L_pen %r / %r, L_final %r / %r (gpu / oracle), K %d, sweeps %d / %d, status %d / %d"
+                  % (label, c, g["L_pen"][c], o["L_pen"][c], g["L_final"][c], o["L_final"][c], o["K"][c],
+                     g["sweeps"][c], o["sweeps"][c], g["status"][c], o["status"][c]))
         lerrs.append(max(eL, eF))
     n = len(list(cells))
     errs, lerrs = np.array(errs), np.array(lerrs)
