@@ -62,6 +62,23 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
 FLOPS_PER_UPDATE = {3: 49, 1: 18}
 JUDGE_REL = 1e-4
 
+# HBM bytes per EM phase of the warm step, from rocprofv3 FETCH_SIZE (x 2.0)
+# and WRITE_SIZE (x 1.0) runs calibrated on a plain device copy (summary and
+# commands in profiles/k_em_weibel_3v_hbm_bytes.md).  Reported only while
+# the EM kernel sources are the ones the counters were taken on.
+EM_TRAFFIC = {"weibel_3v": {"sources_sha256": "f7cebc9480777a770faa7e67403de3d351c280ac64cf45ef73bea50889fe5a06",
+                            "bytes": 334966443}}
+EM_SOURCES = ("gm_compress_impl.h", "gm_compress_d3_f32.hip", "gm_device.h", "gm_launch.h")
+
+
+def em_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in EM_SOURCES:
+        with open(os.path.join(ROOT, "paper_2007_12273_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -73,7 +90,7 @@ def parse():
                    help="warm: learned warm start (the headline); cold: plain EM only")
     p.add_argument("--train-sets", type=int, default=16, help="training batches of cells (seeds 5000+i)")
     p.add_argument("--epochs", type=int, default=50)
-    p.add_argument("--cpu-cells", type=int, default=32, help="cells in the CPU-oracle sample")
+    p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-pool", action="store_true",
                    help="generate the training cells in this process (no child processes; for profiler runs)")
@@ -325,6 +342,8 @@ def main():
         ms, em_ms, visits, phases, Kout, wr = ms_cold, ph_cold["em"], cold["visits"], ph_cold, cold["K"], cold
 
     em_flops = float((counts * visits).sum()) * FLOPS_PER_UPDATE[D]
+    tr = EM_TRAFFIC.get(args.workload)
+    traffic = tr["bytes"] if (warm and tr and tr["sources_sha256"] == em_sources_digest()) else None
     achieved = em_flops / (em_ms * 1e-3) / 1e12
     recon_bytes = n_part * 8 * (D + 1 + dx)
     line = {
@@ -353,7 +372,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
             "flops_per_launch": em_flops,
             "ms_per_launch": em_ms,
         },

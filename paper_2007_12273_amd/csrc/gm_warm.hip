@@ -264,13 +264,25 @@ __global__ void k_loss(const float* Y, const float* T, int B, float lambda, floa
     if (loss) loss[r] = l;
 }
 
-__global__ void k_colsum(const float* X, int rows, int cols, int64_t ld, float* out)
+// column sums: a 32 x 32 block per 32 columns; thread (ty, tx) adds rows
+// ty, ty + 32, ... of column tx, then row 0 adds the 32 partials in order
+constexpr int kColTile = 32;
+__global__ __launch_bounds__(kColTile * kColTile) void k_colsum(const float* X, int rows, int cols, int64_t ld,
+                                                                 float* out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+    __shared__ float part[kColTile][kColTile + 1];
+    const int tx = threadIdx.x % kColTile, ty = threadIdx.x / kColTile;
+    const int j = blockIdx.x * kColTile + tx;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += X[(size_t)r * ld + j];
-    out[j] = s;
+    if (j < cols)
+        for (int r = ty; r < rows; r += kColTile) s += X[(size_t)r * ld + j];
+    part[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && j < cols) {
+        float t = part[0][tx];
+        for (int q = 1; q < kColTile; ++q) t += part[q][tx];
+        out[j] = t;
+    }
 }
 
 __global__ void k_adam(float* w, float* m, float* v, const float* g, uint16_t* wb, int64_t n, float lr, float b1,
@@ -725,7 +737,7 @@ int gm_warm_train_step(gm_warm* m, const uint16_t* feats, const float* targets, 
     g.C32 = m->grad + OFF_W3;
     g.ldc = NO;
     if (gemm(g, st)) return GM_EHIP;
-    hipLaunchKernelGGL(k_colsum, dim3((NO + 127) / 128), dim3(128), 0, st, m->dY, B, NO, (int64_t)NO, m->grad + OFF_B3);
+    hipLaunchKernelGGL(k_colsum, dim3((NO + kColTile - 1) / kColTile), dim3(kColTile * kColTile), 0, st, m->dY, B, NO, (int64_t)NO, m->grad + OFF_B3);
     g = ga(m->dYb, NO, 1, m->wb + OFF_W3, 1, NO, B, NH, NO);
     g.mask = m->H2;
     g.ldm = NH;
@@ -739,7 +751,7 @@ int gm_warm_train_step(gm_warm* m, const uint16_t* feats, const float* targets, 
     g.C32 = m->grad + OFF_W2;
     g.ldc = NH;
     if (gemm(g, st)) return GM_EHIP;
-    hipLaunchKernelGGL(k_colsum, dim3((NH + 127) / 128), dim3(128), 0, st, m->dH2, B, NH, (int64_t)NH, m->grad + OFF_B2);
+    hipLaunchKernelGGL(k_colsum, dim3((NH + kColTile - 1) / kColTile), dim3(kColTile * kColTile), 0, st, m->dH2, B, NH, (int64_t)NH, m->grad + OFF_B2);
     g = ga(m->dH2b, NH, 1, m->wb + OFF_W2, 1, NH, B, NH, NH);
     g.mask = m->H1;
     g.ldm = NH;
@@ -753,7 +765,7 @@ int gm_warm_train_step(gm_warm* m, const uint16_t* feats, const float* targets, 
     g.C32 = m->grad + OFF_W1;
     g.ldc = NH;
     if (gemm(g, st)) return GM_EHIP;
-    hipLaunchKernelGGL(k_colsum, dim3((NH + 127) / 128), dim3(128), 0, st, m->dH1, B, NH, (int64_t)NH, m->grad + OFF_B1);
+    hipLaunchKernelGGL(k_colsum, dim3((NH + kColTile - 1) / kColTile), dim3(kColTile * kColTile), 0, st, m->dH1, B, NH, (int64_t)NH, m->grad + OFF_B1);
     if (launch_ok() != GM_OK) return GM_EHIP;
     m->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
