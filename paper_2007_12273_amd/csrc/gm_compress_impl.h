@@ -31,10 +31,13 @@
 //   c_j  = log2 u_j - D/2 log2(2 pi) - log2 sqrt(det Sigma_j),
 //   A_j  = sqrt(log2(e)/2) L_j^{-1},   Sigma_j = L_j L_j^T,
 // with u_j unnormalised weights (G = sum u_j).  A component update costs one
-// exp2 per particle; the denominator sum_j e_pj is re-summed from the stored
-// terms, so no cancellation builds up.  At the end of every sweep ref_p
-// absorbs log2 of the particle's mixture density, which is the per-particle
-// term of eq. (lnL-GM).
+// exp2 per particle; the denominator sum_j e_pj is updated by the change of
+// the one term, re-summed exactly where most of it cancelled and at the end
+// of every sweep, where ref_p + log2(sum_j e_pj) - log2 G is the particle's
+// log2 mixture density, the per-particle term of eq. (lnL-GM).  A particle
+// whose sum underflows, or whose new term overflows the reference, is
+// rebased: its terms are recomputed about their own maximum (a log2-space
+// log-sum-exp).
 #pragma once
 
 #include "gm_device.h"
@@ -800,20 +803,24 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                 double lsum[1] = {0.0};
                 R dens[P];
                 uint32_t low = 0;
+                if constexpr (STORE_E) {
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    R den;
-                    if constexpr (STORE_E) {
-                        den = resum(e[p]);
-                    } else {
-                        den = R(0);
-                        for (int j = 0; j < Kslots; ++j)
-                            if ((alive >> j) & 1u)
-                                den += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                    for (int p = 0; p < P; ++p) dens[p] = resum(e[p]);
+                } else {
+                    // component outer, particles inner: each component's
+                    // parameters are read from LDS once per sweep
+#pragma unroll
+                    for (int p = 0; p < P; ++p) dens[p] = R(0);
+                    for (int j = 0; j < Kslots; ++j) {
+                        if (!((alive >> j) & 1u)) continue;
+                        const CompState<R, D> cj = comp[j];
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+                            dens[p] += fast_exp2(fmin(log2_term<R, D>(cj, x[p]) - ref[p], R(64)));
                     }
-                    dens[p] = den;
-                    low |= (uint32_t)!(den > rebase_below) << p;
                 }
+#pragma unroll
+                for (int p = 0; p < P; ++p) low |= (uint32_t)!(dens[p] > rebase_below) << p;
                 if (__builtin_amdgcn_ballot_w64(low != 0) != 0) {
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
@@ -829,13 +836,15 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                 for (int p = 0; p < P; ++p) {
                     const R den = dens[p];
                     const R lg = fast_log2(den);
-                    ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
-                    lsum[0] += (double)a[p] * (double)ref[p];
                     if constexpr (STORE_E) {
-                        const R inv = fast_rcp(den);
-                        e[p] *= inv;  // unused slots hold 0
-                        Sden[p] = resum(e[p]);
+                        // the weights are normalised below (u_j / G, c_j - log2 G):
+                        // lowering the reference by log2 G keeps every stored term
+                        ref[p] = ref[p] - lg2G;
+                        lsum[0] += (double)a[p] * (double)(ref[p] + lg);  // log2 mixture density at x_p
+                        Sden[p] = den;
                     } else {
+                        ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
+                        lsum[0] += (double)a[p] * (double)ref[p];
                         Sden[p] = R(1);
                     }
                 }
