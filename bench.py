@@ -92,6 +92,7 @@ def parse():
     p.add_argument("--epochs", type=int, default=50)
     p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     p.add_argument("--no-pool", action="store_true",
                    help="generate the training cells in this process (no child processes; for profiler runs)")
     p.add_argument("--copy-check", action="store_true",
@@ -172,6 +173,34 @@ def time_steps(fn, steps, warmup, torch):
     stop.record()
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / steps
+
+
+def graph_ms(fn, steps, torch):
+    """Capture one step in a HIP graph (torch.cuda.graph on the caller's
+    stream) and time `steps` replays after 3 warm-up replays."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del g
+    times.sort()
+    return times[len(times) // 2]
 
 
 def phase_times(fn, reps, api, torch):
@@ -268,6 +297,12 @@ def main():
 
     ms_cold = time_steps(cold_step, args.steps, args.warmup, torch)
     log("cold: %.3f ms/step" % ms_cold)
+    graph = {}
+    if not args.no_graph:
+        graph["plain_em_median_ms"] = graph_ms(cold_step, max(10, args.steps), torch)
+        if warm:
+            graph["warm_before_judged_fallback_median_ms"] = graph_ms(lambda: warm_step(), max(10, args.steps), torch)
+        log("graph replays: %s" % graph)
     ph_cold = phase_times(cold_step, max(2, min(args.steps, 5)), api, torch)
     cold = {k: t.cpu().numpy() for k, t in comp_c.out.as_dict().items()}
 
@@ -385,6 +420,8 @@ def main():
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
     }
     line.update(line_extra)
+    if graph:
+        line["hip_graph_replay"] = graph
     if args.copy_check:
         src = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
