@@ -93,6 +93,7 @@ def parse():
     p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    p.add_argument("--no-tune", action="store_true", help="keep the built-in EM launch plans (no gm_autotune)")
     p.add_argument("--no-pool", action="store_true",
                    help="generate the training cells in this process (no child processes; for profiler runs)")
     p.add_argument("--copy-check", action="store_true",
@@ -295,6 +296,15 @@ def main():
         r = comp_w(v, alpha, off, init=init)
         recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
+    tune = {}
+    if not args.no_tune:
+        # EM launch plans tuned on this batch, separately for the cold and the
+        # warm start (outside the timed region)
+        tune["plain_em"] = comp_c.autotune(v, alpha, off)
+        if warm:
+            tune["warm"] = comp_w.autotune(v, alpha, off, init=model.initial_mixtures(v, alpha, off, bufs=bufs))
+        torch.cuda.synchronize()
+        log("autotune: %s" % {k: (round(r["builtin_em_ms"], 2), round(r["tuned_em_ms"], 2)) for k, r in tune.items()})
     ms_cold = time_steps(cold_step, args.steps, args.warmup, torch)
     log("cold: %.3f ms/step" % ms_cold)
     graph = {}
@@ -422,6 +432,9 @@ def main():
     line.update(line_extra)
     if graph:
         line["hip_graph_replay"] = graph
+    if tune:
+        line["autotune"] = {k: {"builtin_em_ms": r["builtin_em_ms"], "tuned_em_ms": r["tuned_em_ms"],
+                                "variant": r["variant"], "lane": r["lane"]} for k, r in tune.items()}
     if args.copy_check:
         src = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

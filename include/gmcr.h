@@ -139,6 +139,44 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
                 const gm_opts* o, const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* ---- launch-plan autotuner ----
+ * gm_compress runs the EM iterations in twelve length buckets (bucket b
+ * holds the cells of up to 64 * 2^b particles, refined at kmax 16), each a
+ * persistent launch whose workgroups take cells from a queue, spread over
+ * the caller's stream and three library streams.  A bucket can run with
+ * several launch variants: particles per thread (1, 2, 4, 8, 16), the
+ * matching number of 64-lane waves per workgroup, and density terms kept
+ * in registers or recomputed.  gm_autotune measures, on the caller's batch,
+ * every non-empty bucket alone under each variant, keeps the fastest per
+ * bucket, assigns the buckets to the four streams longest first onto the
+ * least-loaded stream, times the concurrent EM phase of that plan against
+ * the built-in plan, and installs the faster of the two for this device,
+ * D, kmax class (<= 8 or <= 16), precision and kind of start (warm when
+ * init supplies mixtures).  Later gm_compress calls of that kind use it.
+ * Arguments as for gm_compress (converged mode, no fixed sweeps); `out`
+ * holds a complete compress result afterwards.  Synchronous on `stream`;
+ * it must not run while other host threads call gm_compress on the device,
+ * nor with gm_profile enabled (GM_EINVAL).
+ * report: nullable, at least GM_TUNE_REPORT_LEN doubles: [0] EM phase of
+ * the built-in plan (ms), [1] of the tuned plan, [2 + b] bucket b's
+ * fastest standalone time (0 when empty), [14 + b] the installed variant of
+ * bucket b as per_thread * 100 + waves * 10 + (1 if register-resident),
+ * [26 + b] its stream (0-2 library streams, 3 the caller's). */
+#define GM_TUNE_REPORT_LEN 38
+int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                const gm_opts* o, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,
+                void* stream, double* report, int32_t report_len);
+
+/* Install a plan by hand for (D, kmax class, fp64, warm): variant[b] and
+ * (nullable) lane[b] for the twelve buckets, coded as in the report; a
+ * variant must be built (see above) and cover the bucket: 64 * per_thread *
+ * waves >= the bucket's largest cell, waves <= 8.  GM_EINVAL otherwise. */
+int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant,
+                    const int32_t* lane);
+
+/* Forget every tuned plan; gm_compress returns to the built-in plans. */
+int gm_autotune_reset(void);
+
 /* Bytes of workspace gm_reconstruct needs (currently 0; pass NULL). */
 size_t gm_reconstruct_workspace(int64_t n_cells, int32_t D);
 

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmcr.so")
 
 GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL = 0, -1, -2, -3, -4
+GM_TUNE_REPORT_LEN = 38
 
 STATUS = {
     "SMALL_CELL_K1": 1 << 0, "K0_CAPPED": 1 << 1, "COV_FLOOR": 1 << 2, "MAXSWEEPS": 1 << 3,
@@ -39,7 +40,8 @@ class GmInit(ctypes.Structure):
     _fields_ = [(n, P) for n in ("K", "omega", "mu", "sigma")]
 
 
-EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_reconstruct_workspace",
+EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
+           "gm_reconstruct_workspace",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
            "gm_warm_set_params", "gm_warm_gradients", "gm_warm_features", "gm_warm_forward_workspace",
            "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_profile_enable",
@@ -67,6 +69,13 @@ def load():
     L.gm_compress.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmInit),
                               ctypes.POINTER(GmMix), P, ctypes.c_size_t, P]
     L.gm_compress.restype = ctypes.c_int
+    L.gm_autotune.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), ctypes.POINTER(GmInit),
+                              ctypes.POINTER(GmMix), P, ctypes.c_size_t, P, P, ctypes.c_int32]
+    L.gm_autotune.restype = ctypes.c_int
+    L.gm_autotune_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P]
+    L.gm_autotune_set.restype = ctypes.c_int
+    L.gm_autotune_reset.argtypes = []
+    L.gm_autotune_reset.restype = ctypes.c_int
     L.gm_reconstruct_workspace.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.gm_reconstruct_workspace.restype = ctypes.c_size_t
     L.gm_reconstruct.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,

@@ -115,6 +115,32 @@ class Compressor:
         check(rc, "gm_compress")
         return self.out
 
+    def autotune(self, v, alpha, cell_off, init=None, stream=None):
+        """Tune the EM launch plan on this batch (gm_autotune); returns the
+        report as a dict and leaves a complete result in self.out."""
+        _need(v, torch.float64, "v")
+        _need(alpha, torch.float64, "alpha")
+        _need(cell_off, torch.int64, "cell_off")
+        if cell_off.numel() != self.n_cells + 1:
+            raise ValueError("cell_off must have n_cells + 1 entries")
+        ini = None
+        if init is not None:
+            ini = GmInit()
+            for name in ("K", "omega", "mu", "sigma"):
+                t = init[name]
+                _need(t, torch.int32 if name == "K" else torch.float64, "init." + name)
+                setattr(ini, name, t.data_ptr())
+            ini = ctypes.byref(ini)
+        rep = (ctypes.c_double * _lib.GM_TUNE_REPORT_LEN)()
+        rc = _lib.load().gm_autotune(_ptr(v), _ptr(alpha), _ptr(cell_off), self.n_cells, ctypes.byref(self.opts), ini,
+                                     ctypes.byref(self._mix), _ptr(self.ws), self.ws.numel(), _stream(stream), rep,
+                                     _lib.GM_TUNE_REPORT_LEN)
+        check(rc, "gm_autotune")
+        r = list(rep)
+        nb = 12
+        return {"builtin_em_ms": r[0], "tuned_em_ms": r[1], "bucket_ms": r[2:2 + nb],
+                "variant": [int(x) for x in r[2 + nb:2 + 2 * nb]], "lane": [int(x) for x in r[2 + 2 * nb:2 + 3 * nb]]}
+
 
 def compress(v, alpha, cell_off, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False, fixed_sweeps=None,
              init=None, stream=None):
@@ -159,6 +185,18 @@ class Reconstructor:
 def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stream=None):
     r = Reconstructor(out_off, D, dx, device=omega.device)
     return r(K, omega, mu, sigma, target, seed, stream=stream)
+
+
+def autotune_set(D, kmax, variant, lane=None, fp64=False, warm=False):
+    """Install an EM launch plan by hand (codes as in the autotune report)."""
+    va = (ctypes.c_int32 * 12)(*[int(x) for x in variant])
+    la = (ctypes.c_int32 * 12)(*[int(x) for x in lane]) if lane is not None else None
+    check(_lib.load().gm_autotune_set(D, kmax, 1 if fp64 else 0, 1 if warm else 0, va, la), "gm_autotune_set")
+
+
+def autotune_reset():
+    """Forget every tuned EM launch plan."""
+    check(_lib.load().gm_autotune_reset(), "gm_autotune_reset")
 
 
 def profile_enable(on=True):

@@ -4,17 +4,21 @@
 
 #include "gm_compress_impl.h"
 
+#include <algorithm>
+
 namespace gm {
-int launch_compress_d1_float(int, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d3_float(int, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d1_double(int, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d3_double(int, int, const CompressArgs&, int, hipStream_t);
-int grid_compress_d1_float(int, int);
-int grid_compress_d3_float(int, int);
-int grid_compress_d1_double(int, int);
-int grid_compress_d3_double(int, int);
+int launch_compress_d1_float(int, int, bool, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d3_float(int, int, bool, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d1_double(int, int, bool, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d3_double(int, int, bool, int, const CompressArgs&, int, hipStream_t);
+int grid_compress_d1_float(int, int, bool, int);
+int grid_compress_d3_float(int, int, bool, int);
+int grid_compress_d1_double(int, int, bool, int);
+int grid_compress_d3_double(int, int, bool, int);
 int launch_compress_pre_d1(const CompressArgs&, hipStream_t);
 int launch_compress_pre_d3(const CompressArgs&, hipStream_t);
+int launch_compress_requeue_d1(const CompressArgs&, hipStream_t);
+int launch_compress_requeue_d3(const CompressArgs&, hipStream_t);
 int launch_compress_finish_d1(int, const CompressArgs&, hipStream_t);
 int launch_compress_finish_d3(int, const CompressArgs&, hipStream_t);
 }  // namespace gm
@@ -79,6 +83,89 @@ Fork* fork_for_device()
     if (hipEventCreateWithFlags(&f->fork, hipEventDisableTiming) != hipSuccess) return nullptr;
     g_fork[dev] = f;
     return f;
+}
+
+// ---- EM launch plans ------------------------------------------------------
+// Per bucket: launch variant (particles per thread, register-resident
+// densities, waves), stream lane and launch order.  The default plan comes
+// from the bucket tables; gm_autotune replaces it per (device, D, kmax
+// template, precision, warm or cold start) with measured choices.
+struct EmPlan {
+    int8_t per_thread[gm::kNumBuckets];
+    int8_t store_e[gm::kNumBuckets];
+    int8_t waves[gm::kNumBuckets];
+    int8_t lane[gm::kNumBuckets];
+    int8_t order[gm::kNumBuckets];  // launch order, first launched first
+    bool tuned;
+};
+
+EmPlan default_plan(int kt)
+{
+    EmPlan p;
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        const gm::Bucket& c = gm::bucket_cfg(kt, b);
+        p.per_thread[b] = (int8_t)c.per_thread;
+        p.store_e[b] = c.store_e ? 1 : 0;
+        p.waves[b] = (int8_t)c.waves;
+        p.lane[b] = (int8_t)(kt == 8 ? kBucketLane8[b] : kBucketLane16[b]);
+        p.order[b] = (int8_t)(gm::kNumBuckets - 1 - b);  // largest cells first
+    }
+    p.tuned = false;
+    return p;
+}
+
+EmPlan* g_plans[kMaxDevices][2][2][2][2] = {};  // [dev][D == 3][kt == 16][fp64][warm]
+
+EmPlan* plan_slot(int D, int kt, bool fp64, bool warm, bool create)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    EmPlan*& p = g_plans[dev][D == 3][kt == 16][fp64 ? 1 : 0][warm ? 1 : 0];
+    if (!p && create) {
+        p = new EmPlan(default_plan(kt));
+    }
+    return p;
+}
+
+int launch_em_bucket(int D, bool fp64, int kt, int b, const EmPlan& p, gm::CompressArgs& a, int64_t n_cells,
+                     hipStream_t st)
+{
+    const int P = p.per_thread[b], W = p.waves[b];
+    const bool se = p.store_e[b] != 0;
+    int grid = 0;
+    if (D == 1)
+        grid = fp64 ? gm::grid_compress_d1_double(kt, P, se, W) : gm::grid_compress_d1_float(kt, P, se, W);
+    else
+        grid = fp64 ? gm::grid_compress_d3_double(kt, P, se, W) : gm::grid_compress_d3_float(kt, P, se, W);
+    if (grid < 1) return -1;
+    if ((int64_t)grid > n_cells) grid = (int)n_cells;
+    a.bucket = b;
+    a.nwaves = W;
+    if (D == 1)
+        return fp64 ? gm::launch_compress_d1_double(kt, P, se, W, a, grid, st)
+                    : gm::launch_compress_d1_float(kt, P, se, W, a, grid, st);
+    return fp64 ? gm::launch_compress_d3_double(kt, P, se, W, a, grid, st)
+                : gm::launch_compress_d3_float(kt, P, se, W, a, grid, st);
+}
+
+// the EM phase: fork onto the lanes, launch every bucket in plan order, join
+int launch_em_phase(int D, bool fp64, int kt, const EmPlan& p, gm::CompressArgs& a, int64_t n_cells, hipStream_t st)
+{
+    Fork* fk = fork_for_device();
+    if (!fk) return -1;
+    hipStream_t lanes[kLanes] = {fk->aux[0], fk->aux[1], fk->aux[2], st};
+    if (hipEventRecord(fk->fork, st) != hipSuccess) return -1;
+    for (int i = 0; i < kLanes - 1; ++i)
+        if (hipStreamWaitEvent(fk->aux[i], fk->fork, 0) != hipSuccess) return -1;
+    for (int i = 0; i < gm::kNumBuckets; ++i) {
+        const int b = p.order[i];
+        if (launch_em_bucket(D, fp64, kt, b, p, a, n_cells, lanes[p.lane[b]])) return -1;
+    }
+    for (int i = 0; i < kLanes - 1; ++i) {
+        if (hipEventRecord(fk->join[i], fk->aux[i]) != hipSuccess) return -1;
+        if (hipStreamWaitEvent(st, fk->join[i], 0) != hipSuccess) return -1;
+    }
+    return 0;
 }
 
 WsLayout ws_layout(int64_t n_cells, int D)
@@ -174,39 +261,231 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
     prof_mark(EV_EM, st);
     // Length buckets run concurrently on the caller's stream and three
     // auxiliary streams (fork/join through events, so the sequence can be
-    // captured into a graph).  The largest cells are launched first: their
-    // workgroups are the longest-running.
-    Fork* fk = fork_for_device();
-    if (!fk) return GM_EHIP;
-    hipStream_t lanes[kLanes] = {fk->aux[0], fk->aux[1], fk->aux[2], st};
-    if (hipEventRecord(fk->fork, st) != hipSuccess) return GM_EHIP;
-    for (int i = 0; i < kLanes - 1; ++i)
-        if (hipStreamWaitEvent(fk->aux[i], fk->fork, 0) != hipSuccess) return GM_EHIP;
-    for (int b = gm::kNumBuckets - 1; b >= 0; --b) {
-        hipStream_t bs = lanes[kt == 8 ? kBucketLane8[b] : kBucketLane16[b]];
-        int grid = 0;
-        if (D == 1)
-            grid = fp64 ? gm::grid_compress_d1_double(kt, b) : gm::grid_compress_d1_float(kt, b);
-        else
-            grid = fp64 ? gm::grid_compress_d3_double(kt, b) : gm::grid_compress_d3_float(kt, b);
-        if (grid < 1) return GM_EHIP;
-        if ((int64_t)grid > n_cells) grid = (int)n_cells;
-        a.bucket = b;
-        a.nwaves = gm::bucket_cfg(kt, b).waves;
-        if (D == 1)
-            rc = fp64 ? gm::launch_compress_d1_double(kt, b, a, grid, bs) : gm::launch_compress_d1_float(kt, b, a, grid, bs);
-        else
-            rc = fp64 ? gm::launch_compress_d3_double(kt, b, a, grid, bs) : gm::launch_compress_d3_float(kt, b, a, grid, bs);
-        if (rc) return GM_EHIP;
-    }
-    for (int i = 0; i < kLanes - 1; ++i) {
-        if (hipEventRecord(fk->join[i], fk->aux[i]) != hipSuccess) return GM_EHIP;
-        if (hipStreamWaitEvent(st, fk->join[i], 0) != hipSuccess) return GM_EHIP;
+    // captured into a graph), in the order and lanes of the launch plan.
+    {
+        const EmPlan* tuned = plan_slot(D, kt, fp64, init && init->K, false);
+        const EmPlan p = tuned ? *tuned : default_plan(kt);
+        if (launch_em_phase(D, fp64, kt, p, a, n_cells, st)) return GM_EHIP;
     }
     prof_mark(EV_FIN, st);
     rc = D == 1 ? gm::launch_compress_finish_d1(kt, a, st) : gm::launch_compress_finish_d3(kt, a, st);
     prof_mark(EV_END, st);
     return rc ? GM_EHIP : GM_OK;
+}
+
+int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,
+                const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes, void* stream, double* report,
+                int32_t report_len)
+{
+    if (!valid_opts(o) || n_cells < 1 || n_cells > 0x7fffffff || !out) return GM_EINVAL;
+    if (!v || !alpha || !cell_off) return GM_EINVAL;
+    if (!out->K || !out->omega || !out->mu || !out->sigma || !out->moments || !out->L_pen || !out->L_final ||
+        !out->sweeps || !out->status || !out->visits)
+        return GM_EINVAL;
+    if (init && init->K && (!init->omega || !init->mu || !init->sigma)) return GM_EINVAL;
+    if (report && report_len < GM_TUNE_REPORT_LEN) return GM_EINVAL;
+    if (g_prof) return GM_EINVAL;  // the tuner records its own events
+    const WsLayout L = ws_layout(n_cells, o->D);
+    if (!ws || ws_bytes < L.total) return GM_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    gm::CompressArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.alpha = alpha;
+    a.off = cell_off;
+    a.n_cells = n_cells;
+    a.cells = w + L.cells;
+    a.list = (int32_t*)(w + L.list);
+    a.init_idx = (int32_t*)(w + L.init);
+    a.plan = (int32_t*)(w + L.plan);
+    a.kmax = o->kmax;
+    a.n_min = o->n_min;
+    a.max_sweeps = o->max_sweeps;
+    a.tol = o->tol_rel;
+    a.seed = o->seed;
+    a.fixed = nullptr;
+    const bool warm = init && init->K;
+    if (warm) a.init = *init;
+    a.out = *out;
+    const int kt = o->kmax <= 8 ? 8 : 16;
+    const bool fp64 = o->estep_fp64 != 0;
+    const int D = o->D;
+    auto requeue = [&]() { return D == 1 ? gm::launch_compress_requeue_d1(a, st) : gm::launch_compress_requeue_d3(a, st); };
+
+    if (D == 1 ? gm::launch_compress_pre_d1(a, st) : gm::launch_compress_pre_d3(a, st)) return GM_EHIP;
+    int32_t counts[gm::kNumBuckets];
+    if (hipMemcpyAsync(counts, a.plan + gm::PLAN_COUNT, sizeof(counts), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return GM_EHIP;
+
+    // candidate variants of every bucket
+    int cand[gm::kNumBuckets][gm::kNumVariants][2];  // (variant index, waves)
+    int ncand[gm::kNumBuckets];
+    int maxc = 0;
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        ncand[b] = 0;
+        const int max_n = gm::bucket_cfg(kt, b).max_n;
+        for (int vi = 0; vi < gm::kNumVariants; ++vi) {
+            const gm::EmVariant& var = gm::kVariants[vi];
+            if (var.store_e && var.per_thread == 8 && kt != 8) continue;
+            const int waves = (max_n + 64 * var.per_thread - 1) / (64 * var.per_thread);
+            if (waves < 1 || waves > gm::kEmMaxWaves) continue;
+            cand[b][ncand[b]][0] = vi;
+            cand[b][ncand[b]][1] = waves;
+            ++ncand[b];
+        }
+        maxc = std::max(maxc, ncand[b]);
+    }
+
+    hipEvent_t ev[2 * gm::kNumBuckets];
+    for (int i = 0; i < 2 * gm::kNumBuckets; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) return GM_EHIP;
+    int rc = GM_OK;
+    double best_ms[gm::kNumBuckets];
+    int best_c[gm::kNumBuckets];
+    EmPlan trial = default_plan(kt);
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        best_ms[b] = 0.0;
+        best_c[b] = -1;
+    }
+    // every bucket alone on the device, once per candidate
+    for (int r = 0; r < maxc && rc == GM_OK; ++r) {
+        if (requeue()) rc = GM_EHIP;
+        bool used[gm::kNumBuckets] = {};
+        for (int b = gm::kNumBuckets - 1; b >= 0 && rc == GM_OK; --b) {
+            if (counts[b] <= 0 || r >= ncand[b]) continue;
+            const gm::EmVariant& var = gm::kVariants[cand[b][r][0]];
+            trial.per_thread[b] = (int8_t)var.per_thread;
+            trial.store_e[b] = var.store_e ? 1 : 0;
+            trial.waves[b] = (int8_t)cand[b][r][1];
+            if (hipEventRecord(ev[2 * b], st) != hipSuccess ||
+                launch_em_bucket(D, fp64, kt, b, trial, a, n_cells, st) ||
+                hipEventRecord(ev[2 * b + 1], st) != hipSuccess)
+                rc = GM_EHIP;
+            used[b] = true;
+        }
+        if (rc == GM_OK && hipStreamSynchronize(st) != hipSuccess) rc = GM_EHIP;
+        for (int b = 0; b < gm::kNumBuckets && rc == GM_OK; ++b) {
+            if (!used[b]) continue;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[2 * b], ev[2 * b + 1]) != hipSuccess) {
+                rc = GM_EHIP;
+                break;
+            }
+            if (best_c[b] < 0 || t < best_ms[b]) {
+                best_ms[b] = t;
+                best_c[b] = r;
+            }
+        }
+    }
+    // tuned plan: fastest variant per bucket; buckets spread over the lanes
+    // longest first onto the least-loaded lane, and launched in that order
+    EmPlan tuned = default_plan(kt);
+    if (rc == GM_OK) {
+        int idx[gm::kNumBuckets];
+        for (int b = 0; b < gm::kNumBuckets; ++b) {
+            idx[b] = b;
+            if (best_c[b] >= 0) {
+                const gm::EmVariant& var = gm::kVariants[cand[b][best_c[b]][0]];
+                tuned.per_thread[b] = (int8_t)var.per_thread;
+                tuned.store_e[b] = var.store_e ? 1 : 0;
+                tuned.waves[b] = (int8_t)cand[b][best_c[b]][1];
+            }
+        }
+        std::stable_sort(idx, idx + gm::kNumBuckets, [&](int x, int y) { return best_ms[x] > best_ms[y]; });
+        double load[kLanes] = {0, 0, 0, 0};
+        for (int i = 0; i < gm::kNumBuckets; ++i) {
+            const int b = idx[i];
+            int l = 0;
+            for (int q = 1; q < kLanes; ++q)
+                if (load[q] < load[l]) l = q;
+            tuned.lane[b] = (int8_t)l;
+            load[l] += best_ms[b];
+            tuned.order[i] = (int8_t)b;
+        }
+        tuned.tuned = true;
+    }
+    // keep whichever plan runs the concurrent phase faster
+    double phase_ms[2] = {0.0, 0.0};
+    const EmPlan cands[2] = {default_plan(kt), tuned};
+    for (int pi = 0; pi < 2 && rc == GM_OK; ++pi) {
+        double best = 1e30;
+        for (int rep = 0; rep < 2 && rc == GM_OK; ++rep) {
+            float t = 0.f;
+            if (requeue() || hipEventRecord(ev[0], st) != hipSuccess ||
+                launch_em_phase(D, fp64, kt, cands[pi], a, n_cells, st) || hipEventRecord(ev[1], st) != hipSuccess ||
+                hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess)
+                rc = GM_EHIP;
+            best = std::min(best, (double)t);
+        }
+        phase_ms[pi] = best;
+    }
+    const EmPlan& chosen = (rc == GM_OK && phase_ms[1] < phase_ms[0]) ? cands[1] : cands[0];
+    if (rc == GM_OK) {
+        EmPlan* slot = plan_slot(D, kt, fp64, warm, true);
+        if (!slot) rc = GM_EHIP;
+        else *slot = chosen;
+    }
+    // leave a complete compress result in `out`
+    if (rc == GM_OK && (requeue() || launch_em_phase(D, fp64, kt, chosen, a, n_cells, st) ||
+                        (D == 1 ? gm::launch_compress_finish_d1(kt, a, st) : gm::launch_compress_finish_d3(kt, a, st))))
+        rc = GM_EHIP;
+    if (rc == GM_OK && hipStreamSynchronize(st) != hipSuccess) rc = GM_EHIP;
+    for (int i = 0; i < 2 * gm::kNumBuckets; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc == GM_OK && report) {
+        report[0] = phase_ms[0];
+        report[1] = phase_ms[1];
+        for (int b = 0; b < gm::kNumBuckets; ++b) {
+            report[2 + b] = best_ms[b];
+            report[2 + gm::kNumBuckets + b] =
+                chosen.per_thread[b] * 100 + chosen.waves[b] * 10 + (chosen.store_e[b] ? 1 : 0);
+            report[2 + 2 * gm::kNumBuckets + b] = chosen.lane[b];
+        }
+    }
+    return rc;
+}
+
+int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant, const int32_t* lane)
+{
+    if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || !variant) return GM_EINVAL;
+    const int kt = kmax <= 8 ? 8 : 16;
+    EmPlan p = default_plan(kt);
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        const int code = variant[b];
+        const int P = code / 100, W = (code / 10) % 10;
+        const bool se = (code % 10) != 0;
+        bool known = false;
+        for (int vi = 0; vi < gm::kNumVariants; ++vi)
+            known |= gm::kVariants[vi].per_thread == P && gm::kVariants[vi].store_e == se;
+        if (!known || (se && P == 8 && kt != 8) || (code % 10) > 1) return GM_EINVAL;
+        if (W < 1 || W > gm::kEmMaxWaves || 64 * P * W < gm::bucket_cfg(kt, b).max_n) return GM_EINVAL;
+        p.per_thread[b] = (int8_t)P;
+        p.waves[b] = (int8_t)W;
+        p.store_e[b] = se ? 1 : 0;
+        if (lane) {
+            if (lane[b] < 0 || lane[b] >= kLanes) return GM_EINVAL;
+            p.lane[b] = (int8_t)lane[b];
+        }
+    }
+    p.tuned = true;
+    EmPlan* slot = plan_slot(D, kt, fp64 != 0, warm != 0, true);
+    if (!slot) return GM_EHIP;
+    *slot = p;
+    return GM_OK;
+}
+
+int gm_autotune_reset(void)
+{
+    for (auto& a : g_plans)
+        for (auto& b : a)
+            for (auto& c : b)
+                for (auto& d : c)
+                    for (auto& p : d) {
+                        delete p;
+                        p = nullptr;
+                    }
+    return GM_OK;
 }
 
 size_t gm_reconstruct_workspace(int64_t n_cells, int32_t D)

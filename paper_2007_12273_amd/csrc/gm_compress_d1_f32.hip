@@ -3,14 +3,20 @@
 
 namespace gm {
 
-int launch_compress_d1_float(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+int launch_compress_d1_float(int kmax_tpl, int per_thread, bool store_e, int waves, const CompressArgs& a, int grid,
+                          hipStream_t st)
 {
-    return launch_bucket_dr<1, float>(kmax_tpl, bucket, a, grid, st);
+    return launch_bucket_dr<1, float>(kmax_tpl, per_thread, store_e, waves, a, grid, st);
 }
 
-int grid_compress_d1_float(int kmax_tpl, int bucket) { return grid_dr<1, float>(kmax_tpl, bucket); }
+int grid_compress_d1_float(int kmax_tpl, int per_thread, bool store_e, int waves)
+{
+    return grid_dr<1, float>(kmax_tpl, per_thread, store_e, waves);
+}
 
 int launch_compress_pre_d1(const CompressArgs& a, hipStream_t st) { return launch_pre_dr<1>(a, st); }
+
+int launch_compress_requeue_d1(const CompressArgs& a, hipStream_t st) { return launch_requeue_dr<1>(a, st); }
 
 int launch_compress_finish_d1(int kmax_tpl, const CompressArgs& a, hipStream_t st)
 {

@@ -3,11 +3,15 @@
 
 namespace gm {
 
-int launch_compress_d1_double(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+int launch_compress_d1_double(int kmax_tpl, int per_thread, bool store_e, int waves, const CompressArgs& a, int grid,
+                          hipStream_t st)
 {
-    return launch_bucket_dr<1, double>(kmax_tpl, bucket, a, grid, st);
+    return launch_bucket_dr<1, double>(kmax_tpl, per_thread, store_e, waves, a, grid, st);
 }
 
-int grid_compress_d1_double(int kmax_tpl, int bucket) { return grid_dr<1, double>(kmax_tpl, bucket); }
+int grid_compress_d1_double(int kmax_tpl, int per_thread, bool store_e, int waves)
+{
+    return grid_dr<1, double>(kmax_tpl, per_thread, store_e, waves);
+}
 
 }  // namespace gm

@@ -253,6 +253,19 @@ static __global__ void k_plan_reset(int32_t* plan)
     if (threadIdx.x < PLAN_SIZE) plan[threadIdx.x] = 0;
 }
 
+// rewind every bucket's work queue (the autotuner reruns the EM launches)
+static __global__ void k_plan_requeue(int32_t* plan)
+{
+    if (threadIdx.x < kNumBuckets) plan[PLAN_QUEUE + threadIdx.x] = 0;
+}
+
+template <int D>
+int launch_requeue_dr(const CompressArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan_requeue, dim3(1), dim3(64), 0, st, a.plan);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ===========================================================================
 // k_em
 // ===========================================================================
@@ -1190,64 +1203,76 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
 // host-side launch helpers, instantiated per (D, precision) translation unit
 // ===========================================================================
 template <int D, int KMAX, typename R, typename F>
-inline bool with_bucket_kernel(int bucket, F&& f)
+inline bool with_variant_kernel(int per_thread, bool store_e, F&& f)
 {
-    if (bucket < 0 || bucket >= kNumBuckets) return false;
-    const Bucket& b = bucket_cfg(KMAX, bucket);
-    if (!b.store_e) {
-        if (b.per_thread == 8) f(k_em<D, KMAX, 8, false, R>);
-        else f(k_em<D, KMAX, 16, false, R>);
-        return true;
+    if (!store_e) {
+        if (per_thread == 8) {
+            f(k_em<D, KMAX, 8, false, R>);
+            return true;
+        }
+        if (per_thread == 16) {
+            f(k_em<D, KMAX, 16, false, R>);
+            return true;
+        }
+        return false;
     }
-    switch (b.per_thread) {
+    switch (per_thread) {
         case 1: f(k_em<D, KMAX, 1, true, R>); return true;
         case 2: f(k_em<D, KMAX, 2, true, R>); return true;
         case 4: f(k_em<D, KMAX, 4, true, R>); return true;
-        default:
+        case 8:
             if constexpr (KMAX == 8) {
                 f(k_em<D, KMAX, 8, true, R>);
                 return true;
             }
             return false;
+        default: return false;
     }
 }
 
 template <int D, typename R>
-int launch_bucket_dr(int kmax_tpl, int bucket, const CompressArgs& a, int grid, hipStream_t st)
+int launch_bucket_dr(int kmax_tpl, int per_thread, bool store_e, int waves, const CompressArgs& a, int grid,
+                     hipStream_t st)
 {
-    const dim3 g(grid), b(64 * bucket_cfg(kmax_tpl, bucket).waves);
+    if (waves < 1 || waves > kEmMaxWaves || a.nwaves != waves) return -1;
+    const dim3 g(grid), b(64 * waves);
     bool ok = false;
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, a); };
     if (kmax_tpl == 8)
-        ok = with_bucket_kernel<D, 8, R>(bucket, go);
+        ok = with_variant_kernel<D, 8, R>(per_thread, store_e, go);
     else if (kmax_tpl == 16)
-        ok = with_bucket_kernel<D, 16, R>(bucket, go);
+        ok = with_variant_kernel<D, 16, R>(per_thread, store_e, go);
     if (!ok) return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// persistent grid: resident workgroups per CU times the CU count (cached)
 template <int D, typename R>
-int grid_dr(int kmax_tpl, int bucket)
+int grid_dr(int kmax_tpl, int per_thread, bool store_e, int waves)
 {
-    static int cache[2][kNumBuckets] = {};
+    static int cache[2][17][2][kEmMaxWaves + 1] = {};
+    if (per_thread < 1 || per_thread > 16 || waves < 1 || waves > kEmMaxWaves) return 0;
     const int ki = kmax_tpl == 8 ? 0 : 1;
-    if (cache[ki][bucket] > 0) return cache[ki][bucket];
+    int& slot = cache[ki][per_thread][store_e ? 1 : 0][waves];
+    if (slot > 0) return slot;
     int dev = 0, ncu = 0, nb = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const int block = 64 * bucket_cfg(kmax_tpl, bucket).waves;
+    const int block = 64 * waves;
     auto q = [&](auto kern) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), block, 0) !=
             hipSuccess)
             nb = 1;
     };
+    bool ok = false;
     if (kmax_tpl == 8)
-        with_bucket_kernel<D, 8, R>(bucket, q);
+        ok = with_variant_kernel<D, 8, R>(per_thread, store_e, q);
     else
-        with_bucket_kernel<D, 16, R>(bucket, q);
+        ok = with_variant_kernel<D, 16, R>(per_thread, store_e, q);
+    if (!ok) return 0;
     if (nb < 1) nb = 1;
-    cache[ki][bucket] = nb * ncu;
-    return cache[ki][bucket];
+    slot = nb * ncu;
+    return slot;
 }
 
 // pre- and post-EM kernels of one D

@@ -44,6 +44,19 @@ __host__ __device__ constexpr const Bucket& bucket_cfg(int kmax_tpl, int b)
     return kmax_tpl == 8 ? kBuckets8[b] : kBuckets16[b];
 }
 constexpr int kMaxCellParticles = 8192;
+
+// Launch variants a bucket can run with (the autotuner picks among them):
+// particles per thread and whether the density terms stay in registers.
+// A variant fits a bucket when 64 * waves * per_thread >= max_n with
+// waves = ceil(max_n / (64 * per_thread)) <= kEmMaxThreads / 64.
+// Register-resident densities with 8 particles per thread are built for
+// kmax 8 only (16 slots x 8 particles do not fit the register file).
+struct EmVariant {
+    int per_thread;
+    bool store_e;
+};
+constexpr int kNumVariants = 6;
+constexpr EmVariant kVariants[kNumVariants] = {{1, true}, {2, true}, {4, true}, {8, true}, {8, false}, {16, false}};
 constexpr int kEmMaxThreads = 512;
 
 // ---- reconstruct ---------------------------------------------------------

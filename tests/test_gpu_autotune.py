@@ -1,0 +1,89 @@
+"""EM launch plans: every launch variant of every bucket reproduces the
+oracle's replayed sweeps (the autotuner may pick any of them), and the
+autotuner installs a plan that keeps the compress results within the same
+bars."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12273_amd import synth
+
+from gpu_util import dev, host, to_gpu, torch
+from test_gpu_compress import _check_record
+
+pytestmark = pytest.mark.gpu
+
+MAXN16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
+MAXN8 = [64, 128, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 8192]
+VARIANTS = [(1, True), (2, True), (4, True), (8, True), (8, False), (16, False)]
+
+
+def _codes(kmax, variant):
+    P, se = variant
+    if se and P == 8 and kmax > 8:
+        return None
+    out = []
+    for m in (MAXN8 if kmax <= 8 else MAXN16):
+        w = -(-m // (64 * P))
+        if w > 8:
+            out.append(None)
+        else:
+            out.append(P * 100 + w * 10 + (1 if se else 0))
+    return out
+
+
+def _batch():
+    sizes = [40, 64, 100, 128, 200, 256, 400, 512, 700, 768, 900, 1024, 1200, 1280, 1500, 1536, 1700, 1792, 1900,
+             2048, 2500, 3000, 3584, 4096, 5000]
+    parts = [synth.random_cells(300 + i, 1, 3, n, n, k_lo=2, k_hi=4) for i, n in enumerate(sizes)]
+    return synth.concat_cells(parts)
+
+
+@pytest.mark.parametrize("kmax", [8, 16])
+def test_every_variant_matches_oracle_replay(kmax):
+    from paper_2007_12273_amd import api
+    d = _batch()
+    v, a, off = to_gpu(d)
+    o = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=kmax, seed=9, max_sweeps=20)
+    fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
+    default = (MAXN8 if kmax <= 8 else MAXN16)
+    try:
+        for var in VARIANTS:
+            codes = _codes(kmax, var)
+            if codes is None:
+                continue
+            # buckets the variant cannot cover run recomputed densities with
+            # 16 particles per thread
+            fill = [c if c is not None else 1600 + 10 * (-(-default[b] // 1024)) for b, c in enumerate(codes)]
+            api.autotune_set(3, kmax, fill)
+            g = host(api.compress(v, a, off, kmax, seed=9, fixed_sweeps=fs, max_sweeps=20))
+            assert np.array_equal(g["sweeps"], o["sweeps"])
+            _check_record(g, o, 3, k_frac=0.9, par_frac=0.85, par_max=1e-2, label="variant %s kmax %d" % (var, kmax))
+    finally:
+        api.autotune_reset()
+
+
+def test_autotune_installs_a_working_plan():
+    from paper_2007_12273_amd import api
+    d = synth.make("weibel_3v")
+    off = d["cell_off"]
+    nc = 512
+    sub = dict(v=d["v"][:off[nc]], alpha=d["alpha"][:off[nc]], cell_off=off[:nc + 1], D=3)
+    v, a, offg = to_gpu(sub)
+    comp = api.Compressor(nc, 3, 16, device=dev(), seed=2003)
+    try:
+        rep = comp.autotune(v, a, offg)
+        print("autotune:", rep)
+        assert rep["builtin_em_ms"] > 0 and rep["tuned_em_ms"] > 0
+        for code, lane in zip(rep["variant"], rep["lane"]):
+            assert code // 100 in (1, 2, 4, 8, 16) and 0 <= lane <= 3
+        tuned = host(comp.out.as_dict())
+        again = host(comp(v, a, offg).as_dict())
+        for k in ("K", "sweeps", "status"):
+            assert np.array_equal(tuned[k], again[k]), k
+        o = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=16, seed=2003, max_sweeps=60)
+        fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
+        g = host(comp(v, a, offg, fixed_sweeps=fs).as_dict())
+        _check_record(g, o, 3, k_frac=0.95, par_frac=0.9, par_max=1e-2, label="tuned plan replay")
+    finally:
+        api.autotune_reset()
