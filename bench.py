@@ -63,11 +63,12 @@ FLOPS_PER_UPDATE = {3: 49, 1: 18}
 JUDGE_REL = 1e-4
 
 # HBM bytes per EM phase of the warm step, from rocprofv3 FETCH_SIZE (x 2.0)
-# and WRITE_SIZE (x 1.0) runs calibrated on a plain device copy (summary and
-# commands in profiles/k_em_weibel_3v_hbm_bytes.md).  Reported only while
-# the EM kernel sources are the ones the counters were taken on.
-EM_TRAFFIC = {"weibel_3v": {"sources_sha256": "f7cebc9480777a770faa7e67403de3d351c280ac64cf45ef73bea50889fe5a06",
-                            "bytes": 334966443}}
+# and WRITE_SIZE (x 1.0) runs calibrated on a plain device copy, taken with
+# the built-in launch plan (summary and commands in
+# profiles/k_em_weibel_3v_hbm_bytes.md).  Reported only while the EM kernel
+# sources are the ones the counters were taken on.
+EM_TRAFFIC = {"weibel_3v": {"sources_sha256": "eadd9f58927ff0c5256dbeca09e11a8bb5286c075051c5a561d8ad866cc62be3",
+                            "bytes": 333284066, "plan": "built-in launch plan"}}
 EM_SOURCES = ("gm_compress_impl.h", "gm_compress_d3_f32.hip", "gm_device.h", "gm_launch.h")
 
 
@@ -418,6 +419,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": traffic,
+            "traffic_plan": EM_TRAFFIC[args.workload]["plan"] if traffic is not None else None,
             "flops_per_launch": em_flops,
             "ms_per_launch": em_ms,
         },
