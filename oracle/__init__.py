@@ -73,6 +73,9 @@ def _declare(L):
     L.orc_penalised_L.restype = F64
     L.orc_reconstruct.argtypes = [P, P, P, P, ctypes.c_int, P, P, I64, ctypes.c_int, ctypes.c_int, U64,
                                   P, P, P, P, P, ctypes.c_int]
+    L.orc_reconstruct_tensor.argtypes = [P, P, P, P, ctypes.c_int, P, P, I64, ctypes.c_int, ctypes.c_int, U64,
+                                         P, P, P, P, ctypes.c_int]
+    L.orc_reconstruct_tensor.restype = ctypes.c_int
     L.orc_reconstruct.restype = ctypes.c_int
     if hasattr(L, "orc_features"):
         _declare_mlp(L)
@@ -217,6 +220,28 @@ def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stats=False, 
     if stats:
         out["stats"] = sb
     return out
+
+
+def reconstruct_tensor(K, omega, mu, sigma, out_off, moments, D, dx, seed, nthreads=None):
+    """Sampling as reconstruct(); projection matching W, P and the full
+    second moment S of the moments record (W, P, S packed per cell)."""
+    K = _c(K, np.int32)
+    omega = _c(omega, np.float64)
+    kmax = omega.shape[1]
+    off = _c(out_off, np.int64)
+    mom = _c(moments, np.float64)
+    n_cells = len(off) - 1
+    n = int(off[-1])
+    v = np.zeros((n, D))
+    w = np.zeros(n)
+    x = np.zeros((n, dx)) if dx > 0 else None
+    st = np.zeros(n_cells, np.int32)
+    rc = lib().orc_reconstruct_tensor(_p(K), _p(omega), _p(_c(mu, np.float64)), _p(_c(sigma, np.float64)), kmax,
+                                      _p(off), _p(mom), n_cells, D, dx, seed, _p(v), _p(w), _p(x), _p(st),
+                                      nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("orc_reconstruct_tensor rejected its arguments")
+    return {"v": v, "w": w, "x": x, "status": st}
 
 
 def targets_from_moments(moments, D):

@@ -785,6 +785,7 @@ typedef struct {
     double* x_out;
     int32_t* status;
     double* stats; /* nullable: [n_cells * 4] = a (scale), N', |p'|, E' */
+    int tensor;    /* 0: scalar projection (target W, P, E); 1: full second moment (target W, P, S packed) */
 } recon_job;
 
 /* uniform number j (0-based) of particle i in cell c:
@@ -799,13 +800,91 @@ static void particle_uniforms(uint64_t seed, int64_t c, int64_t i, int count, do
     }
 }
 
+/* Cholesky factor of a centred second moment whose pivots are not rounding
+ * noise: every pivot^2 above 1e-12 of ref, the mean diagonal of the
+ * uncentred moment it came from. */
+static int chol_above(int D, const double M[ORC_MAXD][ORC_MAXD], double ref, double L[ORC_MAXD][ORC_MAXD])
+{
+    if (chol(D, M, L) != 0) return -1;
+    for (int d = 0; d < D; ++d)
+        if (!(L[d][d] * L[d][d] > 1e-12 * ref)) return -1;
+    return 0;
+}
+
+/* Projection that matches the full second moment as well: with the sample's
+ * mass N', momentum p', second moment S' and the target's W, P, S,
+ *   v' = P / W + A (v - p' / N'),   A = L_t L_s^-1,
+ * where L_t L_t^T = S - P P^T / W and L_s L_s^T = S' - p' p'^T / N'.  Then
+ * sum w v' = P and sum w v' v'^T = S whenever N' = W (equal weights W / n').
+ * The scalar projection of Sec. 2.4.2 (eqs. alpha, beta) matches tr(S) only;
+ * this one also restores the pressure tensor that the exact-moment step of
+ * Sec. 2.3.1 conserves in the mixture.  Returns the status bits. */
+static int32_t project_tensor(const recon_job* J, int64_t c, const double* tg, int64_t o0, int64_t n)
+{
+    const int D = J->D;
+    double Np = 0.0, pp[ORC_MAXD] = {0, 0, 0}, Sp[ORC_MAXD][ORC_MAXD];
+    memset(Sp, 0, sizeof(Sp));
+    for (int64_t i = 0; i < n; ++i) {
+        const double* vi = J->v_out + (size_t)(o0 + i) * D;
+        const double wi = J->w_out[o0 + i];
+        Np += wi;
+        for (int a = 0; a < D; ++a) {
+            pp[a] += wi * vi[a];
+            for (int b = 0; b < D; ++b) Sp[a][b] += wi * vi[a] * vi[b];
+        }
+    }
+    const double W = tg[0];
+    const double* P = tg + 1;
+    double St[ORC_MAXD][ORC_MAXD], Ss[ORC_MAXD][ORC_MAXD];
+    unpack_sym(D, tg + 1 + D, St);
+    double ref_t = 0.0, ref_s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        ref_t += St[d][d] / D;
+        ref_s += Sp[d][d] / D;
+    }
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) {
+            St[a][b] -= P[a] * P[b] / W;
+            Ss[a][b] = Sp[a][b] - pp[a] * pp[b] / Np;
+        }
+    double Lt[ORC_MAXD][ORC_MAXD], Ls[ORC_MAXD][ORC_MAXD];
+    if (chol_above(D, (const double(*)[ORC_MAXD])St, ref_t, Lt) != 0 ||
+        chol_above(D, (const double(*)[ORC_MAXD])Ss, ref_s, Ls) != 0)
+        return ORC_LEMONS_SKIPPED; /* no projection; the sample stays as drawn */
+    /* A = L_t L_s^-1: solve X L_s = L_t row by row (back substitution) */
+    double Am[ORC_MAXD][ORC_MAXD];
+    for (int r = 0; r < D; ++r)
+        for (int col = D - 1; col >= 0; --col) {
+            double t = Lt[r][col];
+            for (int k = col + 1; k < D; ++k) t -= Am[r][k] * Ls[k][col];
+            Am[r][col] = t / Ls[col][col];
+        }
+    double mean_s[ORC_MAXD];
+    for (int d = 0; d < D; ++d) mean_s[d] = pp[d] / Np;
+    for (int64_t i = 0; i < n; ++i) {
+        double* vi = J->v_out + (size_t)(o0 + i) * D;
+        double dv[ORC_MAXD];
+        for (int d = 0; d < D; ++d) dv[d] = vi[d] - mean_s[d];
+        for (int a = 0; a < D; ++a) {
+            double t = P[a] / W;
+            for (int b = 0; b < D; ++b) t += Am[a][b] * dv[b];
+            vi[a] = t;
+        }
+    }
+    if (J->stats) {
+        J->stats[(size_t)c * 4 + 0] = 1.0;
+        J->stats[(size_t)c * 4 + 1] = Np;
+    }
+    return 0;
+}
+
 static void reconstruct_cell(const recon_job* J, int64_t c)
 {
     const int D = J->D, nt = ntri(D), dx = J->dx;
     const int64_t o0 = J->out_off[c], o1 = J->out_off[c + 1];
     const int64_t n = o1 - o0;
     int32_t st = 0;
-    const double* tg = J->target + (size_t)c * (2 + D);
+    const double* tg = J->target + (size_t)c * (J->tensor ? 1 + D + nt : 2 + D);
     if (J->stats)
         for (int i = 0; i < 4; ++i) J->stats[(size_t)c * 4 + i] = 0.0;
     int K = J->K[c];
@@ -862,6 +941,10 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
         }
         J->w_out[o0 + i] = wp;
         for (int d = 0; d < dx; ++d) J->x_out[(size_t)(o0 + i) * dx + d] = u[1 + 2 * ((D + 1) / 2) + d];
+    }
+    if (J->tensor) {
+        J->status[c] = st | project_tensor(J, c, tg, o0, n);
+        return;
     }
     /* R3: moments of the sample */
     double Np = 0.0, pp[ORC_MAXD] = {0, 0, 0}, Ep = 0.0;
@@ -934,7 +1017,19 @@ int orc_reconstruct(const int32_t* K, const double* w, const double* mu, const d
                     double* v_out, double* w_out, double* x_out, int32_t* status, double* stats, int nthreads)
 {
     if (D < 1 || D > ORC_MAXD || dx < 0 || dx > 3 || kmax < 1 || kmax > ORC_MAXK) return -1;
-    recon_job J = {K, w, mu, S, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out, status, stats};
+    recon_job J = {K, w, mu, S, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out, status, stats, 0};
+    run_chunks(n_cells, nthreads, recon_worker, &J, sizeof(recon_chunk), fill_recon);
+    return 0;
+}
+
+/* Same sampling; the full-second-moment projection with target = the
+ * moments record (W, P, S packed) per cell. */
+int orc_reconstruct_tensor(const int32_t* K, const double* w, const double* mu, const double* S, int kmax,
+                           const int64_t* out_off, const double* moments, int64_t n_cells, int D, int dx,
+                           uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status, int nthreads)
+{
+    if (D < 1 || D > ORC_MAXD || dx < 0 || dx > 3 || kmax < 1 || kmax > ORC_MAXK) return -1;
+    recon_job J = {K, w, mu, S, kmax, out_off, moments, n_cells, D, dx, seed, v_out, w_out, x_out, status, NULL, 1};
     run_chunks(n_cells, nthreads, recon_worker, &J, sizeof(recon_chunk), fill_recon);
     return 0;
 }

@@ -159,3 +159,71 @@ def test_round_trip_preserves_particle_moments():
         assert np.abs(P - (a[:, None] * v).sum(0)).max() / scale < 1e-12
         assert E == pytest.approx(0.5 * (a * (v * v).sum(1)).sum(), rel=1e-12)
         assert counts[c] == sl.stop - sl.start
+
+
+def _tensor_case(D, nc=12, seed=61):
+    d = synth.random_cells(seed, nc, D, 60, 400, k_lo=1, k_hi=4)
+    mix = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=8, seed=3, max_sweeps=40)
+    off = d["cell_off"]
+    return d, mix, off
+
+
+@pytest.mark.parametrize("D", [1, 3])
+def test_tensor_projection_matches_full_second_moment(D):
+    """The full-second-moment projection leaves every cell's sample with the
+    record's W, P and the whole tensor S (not only its trace) to rounding."""
+    d, mix, off = _tensor_case(D)
+    r = oracle.reconstruct_tensor(mix["K"], mix["omega"], mix["mu"], mix["sigma"], off, mix["moments"], D, 1, seed=7)
+    assert (r["status"] & oracle.STATUS["LEMONS_SKIPPED"] == 0).all()
+    iu = np.triu_indices(D)
+    for c in range(len(off) - 1):
+        sl = slice(off[c], off[c + 1])
+        v, w = r["v"][sl], r["w"][sl]
+        m = mix["moments"][c]
+        W, P, S = m[0], m[1:1 + D], m[1 + D:]
+        scale = np.abs(S).max()
+        assert abs(w.sum() - W) <= 1e-13 * W
+        assert np.abs((w[:, None] * v).sum(0) - P).max() <= 1e-12 * np.sqrt(W * scale)
+        Sv = (w[:, None, None] * v[:, :, None] * v[:, None, :]).sum(0)[iu]
+        assert np.abs(Sv - S).max() <= 1e-12 * scale
+
+
+def test_tensor_projection_is_lemons_in_one_dimension():
+    """In 1V the second moment is the energy, and the affine map matching
+    mean and variance is unique: the tensor projection equals eqs. alpha,
+    beta particle by particle."""
+    d, mix, off = _tensor_case(1, seed=62)
+    tg = oracle.targets_from_moments(mix["moments"], 1)
+    a = oracle.reconstruct(mix["K"], mix["omega"], mix["mu"], mix["sigma"], off, tg, 1, 1, seed=9)
+    b = oracle.reconstruct_tensor(mix["K"], mix["omega"], mix["mu"], mix["sigma"], off, mix["moments"], 1, 1, seed=9)
+    np.testing.assert_array_equal(a["status"], b["status"])
+    scale = np.sqrt(tg[:, 2] / tg[:, 0])
+    cell_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    assert (np.abs(a["v"][:, 0] - b["v"][:, 0]) / scale[cell_of]).max() < 1e-12
+    np.testing.assert_array_equal(a["x"], b["x"])
+
+
+def test_tensor_projection_differs_from_scalar_in_3v_and_skips_degenerate():
+    """In 3V the scalar projection matches only tr(S); the tensor one also
+    the off-diagonal entries.  A one-particle cell has no sample covariance:
+    left as drawn and flagged."""
+    d, mix, off = _tensor_case(3, seed=63)
+    tg = oracle.targets_from_moments(mix["moments"], 3)
+    counts = np.diff(off).copy()
+    counts[0] = 1
+    o2 = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    a = oracle.reconstruct(mix["K"], mix["omega"], mix["mu"], mix["sigma"], o2, tg, 3, 0, seed=5)
+    b = oracle.reconstruct_tensor(mix["K"], mix["omega"], mix["mu"], mix["sigma"], o2, mix["moments"], 3, 0, seed=5)
+    assert b["status"][0] == oracle.STATUS["LEMONS_SKIPPED"]
+    iu = np.triu_indices(3)
+    off_diag = [1, 2, 4]
+    worse = 0
+    for c in range(1, len(o2) - 1):
+        sl = slice(o2[c], o2[c + 1])
+        S = mix["moments"][c][4:]
+        Sa = (a["w"][sl, None, None] * a["v"][sl, :, None] * a["v"][sl, None, :]).sum(0)[iu]
+        Sb = (b["w"][sl, None, None] * b["v"][sl, :, None] * b["v"][sl, None, :]).sum(0)[iu]
+        assert np.abs(Sb - S).max() <= 1e-12 * np.abs(S).max()
+        assert abs(Sa[[0, 3, 5]].sum() - S[[0, 3, 5]].sum()) <= 1e-12 * np.abs(S).max()
+        worse += np.abs(Sa[off_diag] - S[off_diag]).max() > 1e-6 * np.abs(S).max()
+    assert worse >= (len(o2) - 2) // 2
