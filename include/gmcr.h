@@ -303,6 +303,26 @@ int gm_warm_targets(const int32_t* K, const double* omega, const double* mu, con
 int gm_warm_train_step(gm_warm* model, const uint16_t* feats, const float* targets, int64_t n_rows,
                        const int32_t* idx, float lr, float lambda, float* loss_rows, void* stream);
 
+/*
+ * gm_reconstruct_tensor -- as gm_reconstruct, with a projection that matches
+ * the whole second-moment tensor of the target, not only its trace.  With
+ * the sample's N', p', S' (sums over the drawn particles) and the target's
+ * W, P, S:
+ *     v' = P / W + A (v - p' / N'),   A = L_t L_s^-1,
+ *     L_t L_t^T = S - P P^T / W,      L_s L_s^T = S' - p' p'^T / N',
+ * so the projected sample has mass W, momentum P and second moment S (the
+ * whole pressure tensor, which the exact-moment step of Sec. 2.3.1 conserves
+ * in the mixture; Lemons' scalar projection of Sec. 2.4.2 matches its trace
+ * only).  In 1V the two projections coincide.  When either centred tensor
+ * has a pivot^2 not above 1e-12 of its mean diagonal (n' <= D, or a
+ * degenerate target) the sample is left as drawn and GM_ST_LEMONS_SKIPPED
+ * is set.  Arguments, layouts and sampling as for gm_reconstruct.
+ */
+int gm_reconstruct_tensor(const int32_t* K, const double* omega, const double* mu, const double* sigma,
+                          int32_t kmax, const int64_t* out_off, const double* target, int64_t n_cells, int32_t D,
+                          int32_t dx, uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* ---- diagnostics ----
  * Phase timing for benchmarks.  While enabled, gm_compress records HIP
  * events on its stream before the moment/plan kernels, before and after the

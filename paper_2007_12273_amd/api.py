@@ -156,7 +156,10 @@ def compress(v, alpha, cell_off, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed
 class Reconstructor:
     """Reusable reconstruct call: owns the output particle arrays."""
 
-    def __init__(self, out_off, D, dx, device="cuda"):
+    def __init__(self, out_off, D, dx, device="cuda", projection="scalar"):
+        if projection not in ("scalar", "tensor"):
+            raise ValueError("projection must be 'scalar' (Lemons) or 'tensor' (full second moment)")
+        self.projection = projection
         self.D, self.dx = D, dx
         self.out_off = out_off
         n = int(out_off[-1].item())
@@ -175,15 +178,17 @@ class Reconstructor:
         kmax = omega.shape[-1]
         if K.numel() != self.n_cells or target.numel() != self.n_cells * (1 + self.D + ntri(self.D)):
             raise ValueError("mixture / target arrays do not match out_off")
-        rc = _lib.load().gm_reconstruct(_ptr(K), _ptr(omega), _ptr(mu), _ptr(sigma), kmax, _ptr(self.out_off),
-                                        _ptr(target), self.n_cells, self.D, self.dx, seed, _ptr(self.v), _ptr(self.w),
-                                        _ptr(self.x), _ptr(self.status), None, 0, _stream(stream))
-        check(rc, "gm_reconstruct")
+        L = _lib.load()
+        fn = L.gm_reconstruct_tensor if self.projection == "tensor" else L.gm_reconstruct
+        rc = fn(_ptr(K), _ptr(omega), _ptr(mu), _ptr(sigma), kmax, _ptr(self.out_off), _ptr(target), self.n_cells,
+                self.D, self.dx, seed, _ptr(self.v), _ptr(self.w), _ptr(self.x), _ptr(self.status), None, 0,
+                _stream(stream))
+        check(rc, "gm_reconstruct_tensor" if self.projection == "tensor" else "gm_reconstruct")
         return {"v": self.v, "w": self.w, "x": self.x, "status": self.status}
 
 
-def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stream=None):
-    r = Reconstructor(out_off, D, dx, device=omega.device)
+def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stream=None, projection="scalar"):
+    r = Reconstructor(out_off, D, dx, device=omega.device, projection=projection)
     return r(K, omega, mu, sigma, target, seed, stream=stream)
 
 

@@ -495,19 +495,19 @@ size_t gm_reconstruct_workspace(int64_t n_cells, int32_t D)
     return 0;
 }
 
-int gm_reconstruct(const int32_t* K, const double* omega, const double* mu, const double* sigma, int32_t kmax,
-                   const int64_t* out_off, const double* target, int64_t n_cells, int32_t D, int32_t dx,
-                   uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status, void* ws,
-                   size_t ws_bytes, void* stream)
+namespace {
+int reconstruct_impl(const int32_t* K, const double* omega, const double* mu, const double* sigma, int32_t kmax,
+                     const int64_t* out_off, const double* target, int64_t n_cells, int32_t D, int32_t dx,
+                     uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status, void* stream,
+                     int tensor)
 {
-    (void)ws;
-    (void)ws_bytes;
     if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || dx < 0 || dx > 3 || n_cells < 0 || n_cells > 0x7fffffff)
         return GM_EINVAL;
     if (n_cells == 0) return GM_OK;
     if (!K || !omega || !mu || !sigma || !out_off || !target || !v_out || !w_out || !status) return GM_EINVAL;
     if (dx > 0 && !x_out) return GM_EINVAL;
     gm::ReconArgs a;
+    memset(&a, 0, sizeof(a));
     a.K = K;
     a.omega = omega;
     a.mu = mu;
@@ -522,10 +522,34 @@ int gm_reconstruct(const int32_t* K, const double* omega, const double* mu, cons
     a.w_out = w_out;
     a.x_out = x_out;
     a.status = status;
+    a.tensor = tensor;
     prof_mark(EV_REC0, (hipStream_t)stream);
     const int rc = gm::launch_reconstruct(a, n_cells, (hipStream_t)stream);
     prof_mark(EV_REC1, (hipStream_t)stream);
     return rc ? GM_EHIP : GM_OK;
+}
+}  // namespace
+
+int gm_reconstruct(const int32_t* K, const double* omega, const double* mu, const double* sigma, int32_t kmax,
+                   const int64_t* out_off, const double* target, int64_t n_cells, int32_t D, int32_t dx,
+                   uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status, void* ws,
+                   size_t ws_bytes, void* stream)
+{
+    (void)ws;
+    (void)ws_bytes;
+    return reconstruct_impl(K, omega, mu, sigma, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out,
+                            status, stream, 0);
+}
+
+int gm_reconstruct_tensor(const int32_t* K, const double* omega, const double* mu, const double* sigma,
+                          int32_t kmax, const int64_t* out_off, const double* target, int64_t n_cells, int32_t D,
+                          int32_t dx, uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status,
+                          void* ws, size_t ws_bytes, void* stream)
+{
+    (void)ws;
+    (void)ws_bytes;
+    return reconstruct_impl(K, omega, mu, sigma, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out,
+                            status, stream, 1);
 }
 
 void gm_profile_enable(int on) { g_prof = on != 0; }

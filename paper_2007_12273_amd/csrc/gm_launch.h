@@ -74,6 +74,7 @@ struct ReconArgs {
     double* w_out;
     double* x_out;
     int32_t* status;
+    int32_t tensor;  // 0: scalar projection (W, P, tr S); 1: full second moment (W, P, S)
 };
 
 int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st);

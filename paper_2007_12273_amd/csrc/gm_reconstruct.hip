@@ -64,13 +64,47 @@ __device__ __forceinline__ void draw_particle(uint64_t seed, int c, int64_t i, i
     for (int d = 0; d < 3; ++d) xpos[d] = (d < dx) ? u[1 + 2 * NPAIR + d] : 0.0;
 }
 
+// Cholesky factor of a packed centred second moment whose pivots are not
+// rounding noise: every pivot^2 above 1e-12 of ref (the mean diagonal of the
+// uncentred moment it came from)
 template <int D>
+__device__ __forceinline__ bool chol_above(const double (&M)[ntri(D)], double ref, double (&L)[ntri(D)])
+{
+    if (!chol<D, double>(M, L)) return false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double l = L[tri_idx<D>(d, d)];
+        if (!(l * l > 1e-12 * ref)) return false;
+    }
+    return true;
+}
+
+// product of packed lower-triangular matrices C = A B
+template <int D>
+__device__ __forceinline__ void tri_mul(const double (&A)[ntri(D)], const double (&B)[ntri(D)], double (&C)[ntri(D)])
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = j; k <= i; ++k) t += A[tri_idx<D>(k, i)] * B[tri_idx<D>(j, k)];
+            C[tri_idx<D>(j, i)] = t;
+        }
+}
+
+// TENSOR: the projection matches the full second moment, v' = P / W +
+// L_t L_s^-1 (v - p' / N') with L_t L_t^T = S - P P^T / W and L_s L_s^T =
+// S' - p' p'^T / N' (the sample's); otherwise Lemons' scalar projection.
+template <int D, bool TENSOR>
 __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
 {
     constexpr int NT = ntri(D);
     constexpr int KM = 16;
+    constexpr int NA = TENSOR ? 1 + D + NT : 2 + D;  // sample sums
     __shared__ double s_mu[KM][D], s_L[KM][NT], s_cum[KM];
-    __shared__ double red[2 * kMaxWaves * (2 + D)];
+    __shared__ double red[2 * kMaxWaves * NA];
     __shared__ int s_bad;
     const int c = blockIdx.x;
     const int tid = threadIdx.x;
@@ -125,18 +159,27 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
     const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
 
     double vr[kReconRegs][D];
-    double acc[2 + D];
+    double acc[NA];
 #pragma unroll
-    for (int t = 0; t < 2 + D; ++t) acc[t] = 0.0;
+    for (int t = 0; t < NA; ++t) acc[t] = 0.0;
     auto add_moments = [&](const double (&v)[D]) {
         acc[0] += wp;
-        double e = 0.0;
+        if constexpr (TENSOR) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            acc[1 + d] += wp * v[d];
-            e += 0.5 * wp * v[d] * v[d];
+            for (int d = 0; d < D; ++d) acc[1 + d] += wp * v[d];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j) acc[1 + D + tri_idx<D>(i, j)] += wp * v[i] * v[j];
+        } else {
+            double e = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                acc[1 + d] += wp * v[d];
+                e += 0.5 * wp * v[d] * v[d];
+            }
+            acc[1 + D] += e;
         }
-        acc[1 + D] += e;
     };
     // pass 1: draw, write weights and positions, reduce N', p', E'
     if (in_regs) {
@@ -160,7 +203,63 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
             add_moments(v);
         }
     }
-    block_sum<2 + D>(acc, red, par, nwaves);
+    block_sum<NA>(acc, red, par, nwaves);
+    if constexpr (TENSOR) {
+        const double Np = acc[0];
+        double St[NT], Ss[NT], ref_t = 0.0, ref_s = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ref_t += tg[1 + D + tri_idx<D>(d, d)] / D;
+            ref_s += acc[1 + D + tri_idx<D>(d, d)] / D;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = i; j < D; ++j) {
+                const int q = tri_idx<D>(i, j);
+                St[q] = tg[1 + D + q] - tg[1 + i] * tg[1 + j] / W;
+                Ss[q] = acc[1 + D + q] - acc[1 + i] * acc[1 + j] / Np;
+            }
+        double Lt[NT], Ls[NT], Li[NT], Am[NT];
+        const bool project = chol_above<D>(St, ref_t, Lt) && chol_above<D>(Ss, ref_s, Ls);
+        double mean_t[D], mean_s[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            mean_t[d] = tg[1 + d] / W;
+            mean_s[d] = acc[1 + d] / Np;
+        }
+        if (project) {
+            tri_inv<D, double>(Ls, Li);
+            tri_mul<D>(Lt, Li, Am);
+        }
+        auto write_t = [&](int64_t i, const double (&v)[D]) {
+            double dv[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) dv[d] = v[d] - mean_s[d];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double t = mean_t[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) t += Am[tri_idx<D>(b, a)] * dv[b];
+                A.v_out[(o0 + i) * D + a] = project ? t : v[a];
+            }
+        };
+        if (in_regs) {
+#pragma unroll
+            for (int j = 0; j < kReconRegs; ++j) {
+                const int64_t i = tid + (int64_t)j * nthreads;
+                if (i < n) write_t(i, vr[j]);
+            }
+        } else {
+            for (int64_t i = tid; i < n; i += nthreads) {
+                double v[D], xp[3];
+                draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, 0, v, xp);
+                write_t(i, v);
+            }
+        }
+        if (tid == 0) A.status[c] = (project ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
+        return;
+    }
     // Lemons: a = sqrt((2 E N' - |P|^2) / (2 E' N' - |p'|^2)), beta = (P - a p') / (a N')
     double E = 0.0;
 #pragma unroll
@@ -212,10 +311,17 @@ int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st)
 {
     if (n_cells == 0) return 0;
     const dim3 grid((unsigned)n_cells), block(kReconThreads);
-    if (a.D == 1)
-        hipLaunchKernelGGL(k_reconstruct<1>, grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL(k_reconstruct<3>, grid, block, 0, st, a);
+    if (a.D == 1) {
+        if (a.tensor)
+            hipLaunchKernelGGL((k_reconstruct<1, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_reconstruct<1, false>), grid, block, 0, st, a);
+    } else {
+        if (a.tensor)
+            hipLaunchKernelGGL((k_reconstruct<3, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_reconstruct<3, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

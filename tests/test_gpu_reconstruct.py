@@ -73,3 +73,43 @@ def test_reconstruct_large_cell_regenerates():
     g = _gpu_recon({"K": K, "omega": w, "mu": mu, "sigma": S}, mom, out_off, D, 1, 9)
     assert np.array_equal(g["status"], o["status"])
     assert np.abs(g["v"] - o["v"]).max() < 1e-12 * np.sqrt(tg[0, 1 + D] / tg[0, 0])
+
+
+@pytest.mark.parametrize("name,nc,dx", [("weibel_3v", 40, 1), ("mix_1v", 40, 0)])
+def test_tensor_reconstruct_matches_oracle(name, nc, dx):
+    """The full-second-moment projection: every particle within 1e-12 of
+    the oracle's, statuses equal (a one-particle cell is skipped), and the
+    projected sample's W, P and whole S equal the record's."""
+    from paper_2007_12273_amd import api
+    d = synth.make(name)
+    off = d["cell_off"]
+    D, kmax = d["D"], d["kmax"]
+    sub = dict(v=d["v"][:off[nc]], alpha=d["alpha"][:off[nc]], cell_off=off[:nc + 1])
+    mix = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=kmax, seed=1, max_sweeps=25)
+    counts = np.diff(sub["cell_off"]).copy()
+    counts[0] = 1
+    counts[1] = 3000  # more particles than the registers hold: regenerated in the second pass
+    out_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    o = oracle.reconstruct_tensor(mix["K"], mix["omega"], mix["mu"], mix["sigma"], out_off, mix["moments"], D, dx,
+                                  seed=4004)
+    g = dev()
+    t = lambda x, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(x)).to(g).to(dt)
+    r = host(api.reconstruct(t(mix["K"], torch.int32), t(mix["omega"]), t(mix["mu"]), t(mix["sigma"]),
+                             t(out_off, torch.int64), t(mix["moments"]), D, dx, 4004, projection="tensor"))
+    assert np.array_equal(r["status"], o["status"])
+    assert o["status"][0] == oracle.STATUS["LEMONS_SKIPPED"] and (o["status"][1:] == 0).all()
+    tg = oracle.targets_from_moments(mix["moments"], D)
+    scale = np.sqrt(np.maximum(tg[:, 1 + D] / tg[:, 0], 1e-300))
+    cell_of = np.repeat(np.arange(nc), counts)
+    err = np.abs(r["v"] - o["v"]).max(axis=1) / scale[cell_of]
+    assert err.max() < 1e-12, err.max()
+    iu = np.triu_indices(D)
+    for c in range(1, nc):
+        sl = slice(out_off[c], out_off[c + 1])
+        w, v = r["w"][sl], r["v"][sl]
+        m = mix["moments"][c]
+        S = m[1 + D:]
+        assert abs(w.sum() - m[0]) <= 1e-13 * m[0]
+        assert np.abs((w[:, None] * v).sum(0) - m[1:1 + D]).max() <= 1e-12 * np.sqrt(m[0] * np.abs(S).max())
+        Sv = (w[:, None, None] * v[:, :, None] * v[:, None, :]).sum(0)[iu]
+        assert np.abs(Sv - S).max() <= 1e-12 * np.abs(S).max()
