@@ -76,6 +76,8 @@ def _declare(L):
     L.orc_reconstruct_tensor.argtypes = [P, P, P, P, ctypes.c_int, P, P, I64, ctypes.c_int, ctypes.c_int, U64,
                                          P, P, P, P, ctypes.c_int]
     L.orc_reconstruct_tensor.restype = ctypes.c_int
+    L.orc_project.argtypes = [P, P, P, P, I64, ctypes.c_int, ctypes.c_int, P]
+    L.orc_project.restype = ctypes.c_int
     L.orc_reconstruct.restype = ctypes.c_int
     if hasattr(L, "orc_features"):
         _declare_mlp(L)
@@ -242,6 +244,21 @@ def reconstruct_tensor(K, omega, mu, sigma, out_off, moments, D, dx, seed, nthre
     if rc != 0:
         raise ValueError("orc_reconstruct_tensor rejected its arguments")
     return {"v": v, "w": w, "x": x, "status": st}
+
+
+def project(v, w, cell_off, moments, D, tensor=False):
+    """Projection of given particles (copies of v, w) towards the moments
+    record: Lemons' scalar form or the full second moment.  Returns
+    (v', status)."""
+    v = np.array(v, dtype=np.float64, order="C").reshape(-1, D)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    off = _c(cell_off, np.int64)
+    n_cells = len(off) - 1
+    st = np.zeros(n_cells, np.int32)
+    rc = lib().orc_project(_p(v), _p(w), _p(off), _p(_c(moments, np.float64)), n_cells, D, int(tensor), _p(st))
+    if rc != 0:
+        raise ValueError("orc_project rejected its arguments")
+    return v, st
 
 
 def targets_from_moments(moments, D):

@@ -812,10 +812,11 @@ static int chol_above(int D, const double M[ORC_MAXD][ORC_MAXD], double ref, dou
 }
 
 /* Projection that matches the full second moment as well: with the sample's
- * mass N', momentum p', second moment S' and the target's W, P, S,
- *   v' = P / W + A (v - p' / N'),   A = L_t L_s^-1,
- * where L_t L_t^T = S - P P^T / W and L_s L_s^T = S' - p' p'^T / N'.  Then
- * sum w v' = P and sum w v' v'^T = S whenever N' = W (equal weights W / n').
+ * mass N', momentum p', second moment S' and the target's P, S,
+ *   v' = P / N' + A (v - p' / N'),   A = L_t L_s^-1,
+ * where L_t L_t^T = S - P P^T / N' and L_s L_s^T = S' - p' p'^T / N'.  Then
+ * sum w v' = P and sum w v' v'^T = S exactly (N' = W for the equal weights
+ * W / n' of the sampling; N' differs after the Gauss'-law correction).
  * The scalar projection of Sec. 2.4.2 (eqs. alpha, beta) matches tr(S) only;
  * this one also restores the pressure tensor that the exact-moment step of
  * Sec. 2.3.1 conserves in the mixture.  Returns the status bits. */
@@ -833,7 +834,6 @@ static int32_t project_tensor(const recon_job* J, int64_t c, const double* tg, i
             for (int b = 0; b < D; ++b) Sp[a][b] += wi * vi[a] * vi[b];
         }
     }
-    const double W = tg[0];
     const double* P = tg + 1;
     double St[ORC_MAXD][ORC_MAXD], Ss[ORC_MAXD][ORC_MAXD];
     unpack_sym(D, tg + 1 + D, St);
@@ -844,7 +844,7 @@ static int32_t project_tensor(const recon_job* J, int64_t c, const double* tg, i
     }
     for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b) {
-            St[a][b] -= P[a] * P[b] / W;
+            St[a][b] -= P[a] * P[b] / Np;
             Ss[a][b] = Sp[a][b] - pp[a] * pp[b] / Np;
         }
     double Lt[ORC_MAXD][ORC_MAXD], Ls[ORC_MAXD][ORC_MAXD];
@@ -866,7 +866,7 @@ static int32_t project_tensor(const recon_job* J, int64_t c, const double* tg, i
         double dv[ORC_MAXD];
         for (int d = 0; d < D; ++d) dv[d] = vi[d] - mean_s[d];
         for (int a = 0; a < D; ++a) {
-            double t = P[a] / W;
+            double t = P[a] / Np;
             for (int b = 0; b < D; ++b) t += Am[a][b] * dv[b];
             vi[a] = t;
         }
@@ -877,6 +877,9 @@ static int32_t project_tensor(const recon_job* J, int64_t c, const double* tg, i
     }
     return 0;
 }
+
+static int32_t project_scalar(const recon_job* J, int64_t c, double W, const double* Pt, double E, int64_t o0,
+                              int64_t n);
 
 static void reconstruct_cell(const recon_job* J, int64_t c)
 {
@@ -946,6 +949,17 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
         J->status[c] = st | project_tensor(J, c, tg, o0, n);
         return;
     }
+    J->status[c] = st | project_scalar(J, c, tg[0], tg + 1, tg[1 + D], o0, n);
+}
+
+/* R3-R5 on the particles of cell c already in v_out, w_out: Lemons'
+ * projection towards momentum P and energy E (eqs. alpha, beta). */
+static int32_t project_scalar(const recon_job* J, int64_t c, double W, const double* Pt, double E, int64_t o0,
+                              int64_t n)
+{
+    (void)W;
+    const int D = J->D;
+    int32_t st = 0;
     /* R3: moments of the sample */
     double Np = 0.0, pp[ORC_MAXD] = {0, 0, 0}, Ep = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -959,10 +973,9 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
     }
     /* R4: scale a and shift beta, eq. (alpha):
      *   a = sqrt((2 E N' - |P|^2) / (2 E' N' - |p'|^2)),  beta = (P - a p') / (a N') */
-    double E = tg[1 + D];
     double P2 = 0.0, pp2 = 0.0;
     for (int d = 0; d < D; ++d) {
-        P2 += tg[1 + d] * tg[1 + d];
+        P2 += Pt[d] * Pt[d];
         pp2 += pp[d] * pp[d];
     }
     double num = 2.0 * E * Np - P2;
@@ -974,7 +987,7 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
     if (num > 1e-12 * (2.0 * E * Np) && den > 1e-12 * (2.0 * Ep * Np)) {
         scale = sqrt(num / den);
         double beta[ORC_MAXD];
-        for (int d = 0; d < D; ++d) beta[d] = (tg[1 + d] - scale * pp[d]) / (scale * Np);
+        for (int d = 0; d < D; ++d) beta[d] = (Pt[d] - scale * pp[d]) / (scale * Np);
         for (int64_t i = 0; i < n; ++i) {
             double* vi = J->v_out + (size_t)(o0 + i) * D;
             for (int d = 0; d < D; ++d) vi[d] = scale * (vi[d] + beta[d]);
@@ -989,7 +1002,7 @@ static void reconstruct_cell(const recon_job* J, int64_t c)
         J->stats[(size_t)c * 4 + 2] = sqrt(pp2);
         J->stats[(size_t)c * 4 + 3] = Ep;
     }
-    J->status[c] = st;
+    return st;
 }
 
 typedef struct {
@@ -1019,6 +1032,39 @@ int orc_reconstruct(const int32_t* K, const double* w, const double* mu, const d
     if (D < 1 || D > ORC_MAXD || dx < 0 || dx > 3 || kmax < 1 || kmax > ORC_MAXK) return -1;
     recon_job J = {K, w, mu, S, kmax, out_off, target, n_cells, D, dx, seed, v_out, w_out, x_out, status, stats, 0};
     run_chunks(n_cells, nthreads, recon_worker, &J, sizeof(recon_chunk), fill_recon);
+    return 0;
+}
+
+/* Projection alone, on particles already in v, w (e.g. after the Gauss'-law
+ * weight correction): target = the moments record (W, P, S packed) per cell;
+ * tensor = 0: Lemons' scalar projection towards P and E = tr(S) / 2;
+ * tensor = 1: the full second moment. */
+int orc_project(double* v, double* w, const int64_t* off, const double* moments, int64_t n_cells, int D,
+                int tensor, int32_t* status)
+{
+    if (D < 1 || D > ORC_MAXD) return -1;
+    const int nt = ntri(D);
+    recon_job J;
+    memset(&J, 0, sizeof(J));
+    J.D = D;
+    J.v_out = v;
+    J.w_out = w;
+    J.tensor = tensor;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const int64_t o0 = off[c], n = off[c + 1] - off[c];
+        const double* tg = moments + (size_t)c * (1 + D + nt);
+        if (n <= 0) {
+            status[c] = 0;
+            continue;
+        }
+        if (tensor) {
+            status[c] = project_tensor(&J, c, tg, o0, n);
+        } else {
+            double E = 0.0;
+            for (int d = 0; d < D; ++d) E += 0.5 * tg[1 + D + d * D - d * (d - 1) / 2];
+            status[c] = project_scalar(&J, c, tg[0], tg + 1, E, o0, n);
+        }
+    }
     return 0;
 }
 

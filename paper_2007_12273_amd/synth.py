@@ -131,7 +131,9 @@ def weibel_3v(seed=1003, n_cells=4096, mean=1000.0):
     counts = lognormal_counts(rng, n_cells, mean)
     v, truth = _sample_cells(rng, counts, 3, 1, 6, aniso=True)
     alpha = np.ones(len(v))
-    return dict(v=v, alpha=alpha, cell_off=_offsets(counts), D=3, kmax=16, dx=1, truth=truth)
+    # cell-local positions on the 1D mesh (drawn last: earlier draws unchanged)
+    x = rng.random((len(v), 1))
+    return dict(v=v, alpha=alpha, x=x, cell_off=_offsets(counts), D=3, kmax=16, dx=1, nx=n_cells, truth=truth)
 
 
 def grid_3v(seed=1004, n_cells=65536, total=1 << 24):
@@ -139,7 +141,12 @@ def grid_3v(seed=1004, n_cells=65536, total=1 << 24):
     counts = lognormal_counts(rng, n_cells, 256.0, total=total if n_cells == 65536 else None)
     v, truth = _sample_cells(rng, counts, 3, 1, 4, aniso=False)
     alpha = rng.uniform(0.5, 1.5, size=len(v))
-    return dict(v=v, alpha=alpha, cell_off=_offsets(counts), D=3, kmax=8, dx=2, truth=truth)
+    # cell-local positions on the 2D mesh, x fastest (drawn last)
+    x = rng.random((len(v), 2))
+    nx = int(round(np.sqrt(n_cells)))
+    if nx * nx != n_cells:
+        nx = n_cells
+    return dict(v=v, alpha=alpha, x=x, cell_off=_offsets(counts), D=3, kmax=8, dx=2, nx=nx, truth=truth)
 
 
 def make(name, seed=None, **kw):
