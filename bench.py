@@ -123,11 +123,11 @@ def training_batches(n_sets, pool=True):
         return pool_.map(_gen_training, seeds)
 
 
-def cpu_baseline(data, W, n_cells_sample, params):
-    """The FP64 oracle of the same path on an evenly spaced sample of the
-    cells, all host threads (capped at 16): warm start (features, FP64
-    perceptron with the trained weights, decode) when params is given, then
-    compress and reconstruct."""
+def cpu_baseline(data, W, n_cells_sample):
+    """The FP64 oracle on an evenly spaced sample of the cells, all host
+    threads (capped at 16): plain cold-start compress, then reconstruct.  The
+    oracle's warm path would need network weights, and those come only from
+    training on the GPU, which the oracle never takes as input."""
     import numpy as np
 
     import oracle
@@ -146,21 +146,15 @@ def cpu_baseline(data, W, n_cells_sample, params):
     threads = oracle.default_threads()
     oracle.build()
     t0 = time.perf_counter()
-    init = None
-    if params is not None:
-        f, fr = oracle.features(v, a, so)
-        _, _, Y = oracle.mlp_forward(f, params)
-        init = oracle.warm_decode(Y, fr, so, W["kmax"])
-    r = oracle.compress(v, a, so, kmax=W["kmax"], seed=W["init_seed"], init=init, nthreads=threads)
+    r = oracle.compress(v, a, so, kmax=W["kmax"], seed=W["init_seed"], nthreads=threads)
     tg = oracle.targets_from_moments(r["moments"], W["D"])
     oracle.reconstruct(r["K"], r["omega"], r["mu"], r["sigma"], so, tg, W["D"], W["dx"], seed=W["recon_seed"],
                        nthreads=threads)
     dt = time.perf_counter() - t0
     npart = int(so[-1])
     return {"value": npart / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d cells (evenly spaced), %d particles, %s start, compress to convergence + "
-                      "reconstruct, %.1f s wall" % (n_cells_sample, n_cells, npart,
-                                                    "learned warm" if params is not None else "cold", dt)}
+            "sample": "%d of %d cells (evenly spaced), %d particles, cold start, compress to convergence + "
+                      "reconstruct, %.1f s wall" % (n_cells_sample, n_cells, npart, dt)}
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -219,6 +213,47 @@ def phase_times(fn, reps, api, torch):
             ph["warm_init"].append(t)
     api.profile_enable(False)
     return {k: float(np.mean(x)) for k, x in ph.items() if x}
+
+
+def restart_chain(data, W, off, comp, recon, reps, api, torch):
+    """The Gauss'-law weight correction (Sec. 2.4.1) after the last cold
+    reconstruct, towards the deposit of the original particles, then the
+    projection with the corrected mass: median times over `reps` runs, each
+    from the reconstructed weights."""
+    import numpy as np
+    dev = off.device
+    n_cells = off.numel() - 1
+    gl = api.GaussLaw(n_cells, W["dx"], data["nx"], device=dev)
+    x0 = torch.from_numpy(data["x"]).to(dev)
+    a0 = torch.from_numpy(data["alpha"]).to(dev)
+    v0, w0 = recon.v.clone(), recon.w.clone()
+    w, v = w0.clone(), v0.clone()
+    r = comp.out
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    t_dep, t_cor, t_prj, iters = [], [], [], []
+    for _ in range(reps):
+        w.copy_(w0)
+        v.copy_(v0)
+        e = [ev() for _ in range(4)]
+        e[0].record()
+        tgt = gl.deposit(x0, a0, off)
+        e[1].record()
+        it, res = gl.correct(recon.x, w, off, tgt, tol=1e-13)
+        e[2].record()
+        _, st = api.project(v, w, off, r.moments, tensor=False, out=v)
+        e[3].record()
+        torch.cuda.synchronize()
+        t_dep.append(e[0].elapsed_time(e[1]))
+        t_cor.append(e[1].elapsed_time(e[2]))
+        t_prj.append(e[2].elapsed_time(e[3]))
+        iters.append(it)
+    med = lambda x: float(np.median(x))
+    Np = np.add.reduceat(w.cpu().numpy(), data["cell_off"][:-1])
+    dm = float(np.abs(Np / r.moments.view(n_cells, -1)[:, 0].cpu().numpy() - 1).max())
+    return {"deposit_ms": med(t_dep), "gauss_correct_ms": med(t_cor), "bicgstab_iterations": int(np.median(iters)),
+            "final_rel_residual": res, "project_ms": med(t_prj),
+            "projected_cell_frac": float((st == 0).float().mean().item()), "max_rel_mass_change": dm,
+            "projection": "scalar (Lemons)"}
 
 
 def subset_gpu(v, alpha, off_host, cells, torch):
@@ -432,6 +467,8 @@ def main():
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
     }
     line.update(line_extra)
+    if "x" in data:  # workloads with particle positions
+        line["restart_chain"] = restart_chain(data, W, off, comp_c, recon, max(3, min(args.steps, 10)), api, torch)
     if graph:
         line["hip_graph_replay"] = graph
     if tune:
@@ -446,13 +483,7 @@ def main():
         line["copy_check_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        params = None
-        if warm:
-            flat = model.get_params()
-            P = api.flat_to_params(flat.astype(np.float64))
-            P["W1"] = P["W1"][:105]
-            params = P
-        line["cpu_baseline"] = cpu_baseline(data, W, args.cpu_cells, params)
+        line["cpu_baseline"] = cpu_baseline(data, W, args.cpu_cells)
     print(json.dumps(line))
 
 

@@ -51,6 +51,7 @@ extern "C" {
 #define GM_EHIP (-2)      /* a HIP runtime call failed */
 #define GM_ENOMEM (-3)    /* workspace missing or smaller than required */
 #define GM_ENOTIMPL (-4)  /* combination not built into this library */
+#define GM_ENOCONV (-5)   /* iterative solve stopped above its tolerance */
 
 /* ---- per-cell status bits ---- */
 #define GM_ST_SMALL_CELL_K1 (1 << 0)   /* n <= n_min: single Gaussian with the cell's moments */
@@ -322,6 +323,68 @@ int gm_reconstruct_tensor(const int32_t* K, const double* omega, const double* m
                           int32_t kmax, const int64_t* out_off, const double* target, int64_t n_cells, int32_t D,
                           int32_t dx, uint64_t seed, double* v_out, double* w_out, double* x_out, int32_t* status,
                           void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gm_project -- the projection of gm_reconstruct (tensor = 0, Lemons'
+ * scalar form) or of gm_reconstruct_tensor (tensor = 1) applied to given
+ * particles: v [n_tot * D] and w [n_tot] FP64 grouped by cell_off [n_cells
+ * + 1], towards the moments record `moments` [n_cells * (1 + D + D(D+1)/2)]
+ * (W, P, S packed) of each cell.  N', p' and S' (or E') are the sums over
+ * the given weights, so after a change of the weights (the Gauss'-law
+ * correction below) the projected particles carry momentum P and second
+ * moment S (or energy tr(S) / 2) with the new mass N'.  v_out [n_tot * D]
+ * may equal v (in place).  Status bits as gm_reconstruct (0 or
+ * GM_ST_LEMONS_SKIPPED; empty cells 0).  D in {1, 3}.
+ */
+int gm_project(const double* v, const double* w, const int64_t* cell_off, const double* moments, int64_t n_cells,
+               int32_t D, int32_t tensor, double* v_out, int32_t* status, void* stream);
+
+/* ---- Gauss'-law weight correction (Sec. 2.4.1) ----
+ * The resampled particles must deposit the charge density the original
+ * ones did.  The mesh is periodic with unit cells: dx = 1, n_cells cells in
+ * a row (nx = n_cells, or nx <= 0); dx = 2, nx * (n_cells / nx) cells, cell c
+ * at (c % nx, c / nx).  Cell i has centre X_i = i + 1/2 (per axis); a
+ * particle of cell c with cell-local position x in [0,1)^dx (the x_out of
+ * gm_reconstruct) sits at X = (cell coordinates) + x.  Charge goes to the
+ * mesh with the quadratic B-spline S2 (3 cells per axis):
+ *     D_i = sum_p w_p S2(X_i - X_p)        (unit charge; rho_i times volume)
+ * The per-cell corrections dA solve M dA = D_target - D(w) with
+ * M_ij = sum_{p in cell j} S2(X_i - X_p) (the top-hat S0 selects the
+ * particles of cell j, eq. p-weight-correction), and w'_p = w_p +
+ * dA_{cell(p)} (eq. new-p-weight).  Sums are FP64 in a fixed order.
+ *
+ * Workspace (device, caller-owned, for both calls) of gm_gauss_workspace
+ * bytes: 2 * 9 (2D; 3 in 1D) + 9 doubles per cell plus 16 bytes per 256
+ * cells and the solver state, 256-byte aligned pieces.  Returns 0 for bad
+ * arguments (dx not 1 or 2, n_cells < 1).
+ */
+size_t gm_gauss_workspace(int64_t n_cells, int32_t dx);
+
+/* gm_deposit -- D_i of the particles x [n_tot * dx], w [n_tot] grouped by
+ * cell_off into dep [n_cells] (FP64, device).  Enqueued on stream. */
+int gm_deposit(const double* x, const double* w, const int64_t* cell_off, int64_t n_cells, int32_t dx, int32_t nx,
+               double* dep, void* ws, size_t ws_bytes, void* stream);
+
+/* gm_gauss_correct -- weights w [n_tot] (in place) corrected so that the
+ * deposit of (x, w) equals dep_target [n_cells].  M dA = b is solved by
+ * BiCGSTAB with the preconditioner diag(M) on the right, from dA = 0, until
+ * the true residual |b - M dA| is at most tol |b| (0 < tol < 1), within
+ * max_iter iterations in all (restarts from the true residual included).
+ * Every cell must hold at least one particle (else GM_EINVAL, weights
+ * untouched).  In 1D, M is then strictly diagonally dominant by columns
+ * (each particle puts at least half its spline on its own cell, more unless
+ * it sits on the cell's edge) and nonsingular; in 2D it is not dominant but
+ * nonsingular for generic positions.  The iteration's scalars stay on the
+ * device; the call reads them back once per 8 iterations and per restart,
+ * so it synchronises `stream` and cannot be captured in a graph; the empty
+ * cell check and GM_ENOCONV come from those reads, after kernels on the
+ * workspace were enqueued.  iters_out (iterations) and resid_out (final
+ * true relative residual) are host pointers, may be NULL.  Returns
+ * GM_ENOCONV, with the weights corrected by the last iterate, when the
+ * tolerance was not reached. */
+int gm_gauss_correct(const double* x, double* w, const int64_t* cell_off, int64_t n_cells, int32_t dx, int32_t nx,
+                     const double* dep_target, double tol, int32_t max_iter, void* ws, size_t ws_bytes, void* stream,
+                     int32_t* iters_out, double* resid_out);
 
 /* ---- diagnostics ----
  * Phase timing for benchmarks.  While enabled, gm_compress records HIP

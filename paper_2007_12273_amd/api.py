@@ -192,6 +192,69 @@ def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stream=None, 
     return r(K, omega, mu, sigma, target, seed, stream=stream)
 
 
+def project(v, w, cell_off, moments, tensor=False, out=None, stream=None):
+    """Projection of given particles (v [n, D], w [n]) towards each cell's
+    moments record, with the mass N' = sum w (gm_project).  Returns
+    (v', status); out may be v (in place)."""
+    _need(v, torch.float64, "v")
+    _need(w, torch.float64, "w")
+    _need(cell_off, torch.int64, "cell_off")
+    _need(moments, torch.float64, "moments")
+    D = v.shape[1]
+    n_cells = cell_off.numel() - 1
+    if w.numel() != v.shape[0] or moments.numel() != n_cells * (1 + D + ntri(D)):
+        raise ValueError("v, w, moments do not match cell_off")
+    out = out if out is not None else torch.empty_like(v)
+    _need(out, torch.float64, "out")
+    status = torch.empty(n_cells, dtype=torch.int32, device=v.device)
+    check(_lib.load().gm_project(_ptr(v), _ptr(w), _ptr(cell_off), _ptr(moments), n_cells, D, 1 if tensor else 0,
+                                 _ptr(out), _ptr(status), _stream(stream)), "gm_project")
+    return out, status
+
+
+class GaussLaw:
+    """Gauss'-law weight correction on a periodic mesh (dx = 1: n_cells in a
+    row; dx = 2: nx * (n_cells / nx)); owns the solver workspace."""
+
+    def __init__(self, n_cells, dx, nx=None, device="cuda"):
+        self.n_cells, self.dx = n_cells, dx
+        self.nx = nx if nx is not None else n_cells
+        nb = _lib.load().gm_gauss_workspace(n_cells, dx)
+        if nb == 0:
+            raise ValueError("bad mesh: n_cells=%d dx=%d" % (n_cells, dx))
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+
+    def _check(self, x, w, cell_off):
+        _need(x, torch.float64, "x")
+        _need(w, torch.float64, "w")
+        _need(cell_off, torch.int64, "cell_off")
+        if cell_off.numel() != self.n_cells + 1 or x.numel() != w.numel() * self.dx:
+            raise ValueError("x, w do not match the mesh")
+
+    def deposit(self, x, w, cell_off, out=None, stream=None):
+        """Charge D_i = sum_p w_p S2(X_i - X_p) on every mesh cell."""
+        self._check(x, w, cell_off)
+        out = out if out is not None else torch.empty(self.n_cells, dtype=torch.float64, device=w.device)
+        _need(out, torch.float64, "out")
+        check(_lib.load().gm_deposit(_ptr(x), _ptr(w), _ptr(cell_off), self.n_cells, self.dx, self.nx, _ptr(out),
+                                     _ptr(self.ws), self.ws.numel(), _stream(stream)), "gm_deposit")
+        return out
+
+    def correct(self, x, w, cell_off, target, tol=1e-13, max_iter=200, stream=None):
+        """Correct w in place so that deposit(x, w) = target; returns
+        (iterations, relative residual).  Raises if the solve stalls."""
+        self._check(x, w, cell_off)
+        _need(target, torch.float64, "target")
+        if target.numel() != self.n_cells:
+            raise ValueError("target must hold one value per mesh cell")
+        it, res = ctypes.c_int32(0), ctypes.c_double(0.0)
+        rc = _lib.load().gm_gauss_correct(_ptr(x), _ptr(w), _ptr(cell_off), self.n_cells, self.dx, self.nx,
+                                          _ptr(target), tol, max_iter, _ptr(self.ws), self.ws.numel(), _stream(stream),
+                                          ctypes.byref(it), ctypes.byref(res))
+        check(rc, "gm_gauss_correct")
+        return it.value, res.value
+
+
 def autotune_set(D, kmax, variant, lane=None, fp64=False, warm=False):
     """Install an EM launch plan by hand (codes as in the autotune report)."""
     va = (ctypes.c_int32 * 12)(*[int(x) for x in variant])

@@ -552,6 +552,25 @@ int gm_reconstruct_tensor(const int32_t* K, const double* omega, const double* m
                             status, stream, 1);
 }
 
+int gm_project(const double* v, const double* w, const int64_t* cell_off, const double* moments, int64_t n_cells,
+               int32_t D, int32_t tensor, double* v_out, int32_t* status, void* stream)
+{
+    if ((D != 1 && D != 3) || (tensor != 0 && tensor != 1) || n_cells < 0 || n_cells > 0x7fffffff)
+        return GM_EINVAL;
+    if (n_cells == 0) return GM_OK;
+    if (!v || !w || !cell_off || !moments || !v_out || !status) return GM_EINVAL;
+    gm::ProjArgs a;
+    a.v = v;
+    a.w = w;
+    a.off = cell_off;
+    a.moments = moments;
+    a.D = D;
+    a.tensor = tensor;
+    a.v_out = v_out;
+    a.status = status;
+    return gm::launch_project(a, n_cells, (hipStream_t)stream) ? GM_EHIP : GM_OK;
+}
+
 void gm_profile_enable(int on) { g_prof = on != 0; }
 
 int gm_profile_read(double* ms, int n)
@@ -578,6 +597,7 @@ const char* gm_strerror(int code)
         case GM_EHIP: return "HIP runtime error";
         case GM_ENOMEM: return "workspace missing or too small";
         case GM_ENOTIMPL: return "not implemented in this build";
+        case GM_ENOCONV: return "iterative solve did not reach its tolerance";
         default: return "unknown error";
     }
 }

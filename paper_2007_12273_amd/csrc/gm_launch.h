@@ -79,4 +79,18 @@ struct ReconArgs {
 
 int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st);
 
+// arguments of the projection of given particles
+struct ProjArgs {
+    const double* v;
+    const double* w;
+    const int64_t* off;
+    const double* moments;
+    int32_t D;
+    int32_t tensor;
+    double* v_out;
+    int32_t* status;
+};
+
+int launch_project(const ProjArgs& a, int64_t n_cells, hipStream_t st);
+
 }  // namespace gm

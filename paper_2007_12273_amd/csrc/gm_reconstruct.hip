@@ -1,6 +1,9 @@
 // gm_reconstruct.hip -- per-cell ancestral sampling of a Gaussian mixture
-// (Sec. 2.4, eq. mix-dist-1) followed by Lemons' moment-matching projection
-// (Sec. 2.4.2, eqs. alpha/beta), FP64 throughout.
+// (Sec. 2.4, eq. mix-dist-1) followed by a moment-matching projection, FP64
+// throughout: Lemons' scalar form (Sec. 2.4.2, eqs. alpha/beta) or the one
+// that matches the whole second-moment tensor; and the projection alone, of
+// particles whose weights changed after sampling (the Gauss'-law correction
+// of Sec. 2.4.1).
 //
 // One workgroup per cell.  Every particle is generated once from its own
 // Philox counter; up to RP particles per thread stay in registers between
@@ -94,17 +97,146 @@ __device__ __forceinline__ void tri_mul(const double (&A)[ntri(D)], const double
         }
 }
 
-// TENSOR: the projection matches the full second moment, v' = P / W +
-// L_t L_s^-1 (v - p' / N') with L_t L_t^T = S - P P^T / W and L_s L_s^T =
-// S' - p' p'^T / N' (the sample's); otherwise Lemons' scalar projection.
+// Sums of a particle set that the projections need: N' = sum w, p' =
+// sum w v and either S' = sum w v v^T (packed, TENSOR) or E' = sum w |v|^2 / 2.
+template <int D, bool TENSOR>
+struct SampleSums {
+    static constexpr int NT = ntri(D);
+    static constexpr int NA = TENSOR ? 1 + D + NT : 2 + D;
+    double acc[NA];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int t = 0; t < NA; ++t) acc[t] = 0.0;
+    }
+    __device__ __forceinline__ void add(const double (&v)[D], double w)
+    {
+        acc[0] += w;
+        if constexpr (TENSOR) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc[1 + d] += w * v[d];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j) acc[1 + D + tri_idx<D>(i, j)] += w * v[i] * v[j];
+        } else {
+            double e = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                acc[1 + d] += w * v[d];
+                e += 0.5 * w * v[d] * v[d];
+            }
+            acc[1 + D] += e;
+        }
+    }
+};
+
+// The per-cell affine map of the projection, from the sample sums and the
+// target moments record tg = (W, P, S packed).
+//   TENSOR: v' = P / N' + A (v - p' / N'), A = L_t L_s^-1 with L_t L_t^T =
+//     S - P P^T / N' and L_s L_s^T = S' - p' p'^T / N', so sum w v' = P and
+//     sum w v' v'^T = S; skipped when a pivot^2 of either factor is not
+//     above 1e-12 of the mean diagonal of its uncentred moment.
+//   otherwise Lemons' scalar form (Sec. 2.4.2, eqs. alpha/beta) towards P and
+//     E = tr(S) / 2: v' = a (v + beta), a = sqrt((2 E N' - |P|^2) / (2 E' N'
+//     - |p'|^2)), beta = (P - a p') / (a N'); skipped when either bracket is
+//     not above 1e-12 of its leading term 2 E N' or 2 E' N' (zero to
+//     rounding: the denominator vanishes exactly when all velocities
+//     coincide, as for n' = 1).
+template <int D, bool TENSOR>
+struct Projection {
+    static constexpr int NT = ntri(D);
+    bool ok;
+    double shift[D];  // TENSOR: P / N'; scalar: beta
+    double mean_s[D];
+    double Am[NT];
+    double sc;
+    __device__ __forceinline__ void setup(const double (&acc)[SampleSums<D, TENSOR>::NA], const double* tg)
+    {
+        const double Np = acc[0];
+        if constexpr (TENSOR) {
+            double St[NT], Ss[NT], ref_t = 0.0, ref_s = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                ref_t += tg[1 + D + tri_idx<D>(d, d)] / D;
+                ref_s += acc[1 + D + tri_idx<D>(d, d)] / D;
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j) {
+                    const int q = tri_idx<D>(i, j);
+                    St[q] = tg[1 + D + q] - tg[1 + i] * tg[1 + j] / Np;
+                    Ss[q] = acc[1 + D + q] - acc[1 + i] * acc[1 + j] / Np;
+                }
+            double Lt[NT], Ls[NT], Li[NT];
+            ok = chol_above<D>(St, ref_t, Lt) && chol_above<D>(Ss, ref_s, Ls);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                shift[d] = tg[1 + d] / Np;
+                mean_s[d] = acc[1 + d] / Np;
+            }
+            if (ok) {
+                tri_inv<D, double>(Ls, Li);
+                tri_mul<D>(Lt, Li, Am);
+            }
+        } else {
+            double E = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) E += tg[1 + D + tri_idx<D>(d, d)];
+            E *= 0.5;
+            const double Ep = acc[1 + D];
+            double P2 = 0.0, pp2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                P2 += tg[1 + d] * tg[1 + d];
+                pp2 += acc[1 + d] * acc[1 + d];
+            }
+            const double num = 2.0 * E * Np - P2;
+            const double den = 2.0 * Ep * Np - pp2;
+            ok = num > 1e-12 * (2.0 * E * Np) && den > 1e-12 * (2.0 * Ep * Np);
+            sc = 1.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) shift[d] = 0.0;
+            if (ok) {
+                sc = sqrt(num / den);
+#pragma unroll
+                for (int d = 0; d < D; ++d) shift[d] = (tg[1 + d] - sc * acc[1 + d]) / (sc * Np);
+            }
+        }
+    }
+    // writes the image of v (v itself when the projection was skipped)
+    __device__ __forceinline__ void write(const double (&v)[D], double* out) const
+    {
+        if constexpr (TENSOR) {
+            double dv[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) dv[d] = v[d] - mean_s[d];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double t = shift[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) t += Am[tri_idx<D>(b, a)] * dv[b];
+                out[a] = ok ? t : v[a];
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d) out[d] = ok ? sc * (v[d] + shift[d]) : v[d];
+        }
+    }
+};
+
+// One workgroup per cell: draw the cell's n' particles, reduce their sums,
+// then write the projected velocities (TENSOR: full second moment; else
+// Lemons' scalar form).
 template <int D, bool TENSOR>
 __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
 {
     constexpr int NT = ntri(D);
     constexpr int KM = 16;
-    constexpr int NA = TENSOR ? 1 + D + NT : 2 + D;  // sample sums
+    using Sums = SampleSums<D, TENSOR>;
     __shared__ double s_mu[KM][D], s_L[KM][NT], s_cum[KM];
-    __shared__ double red[2 * kMaxWaves * NA];
+    __shared__ double red[2 * kMaxWaves * Sums::NA];
     __shared__ int s_bad;
     const int c = blockIdx.x;
     const int tid = threadIdx.x;
@@ -151,37 +283,16 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
         s_cum[K - 1] = 1.0;
     }
     __syncthreads();
-    // targets from the compress moments record: W, P = sum alpha v, and
-    // E = tr(S) / 2 with S = sum alpha v v^T
+    // targets from the compress moments record: W, P = sum alpha v, S = sum
+    // alpha v v^T (the scalar projection takes E = tr(S) / 2)
     const double* tg = A.target + (size_t)c * nmom(D);
-    const double W = tg[0];
-    const double wp = W / (double)n;
+    const double wp = tg[0] / (double)n;
     const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
 
     double vr[kReconRegs][D];
-    double acc[NA];
-#pragma unroll
-    for (int t = 0; t < NA; ++t) acc[t] = 0.0;
-    auto add_moments = [&](const double (&v)[D]) {
-        acc[0] += wp;
-        if constexpr (TENSOR) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) acc[1 + d] += wp * v[d];
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int j = i; j < D; ++j) acc[1 + D + tri_idx<D>(i, j)] += wp * v[i] * v[j];
-        } else {
-            double e = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                acc[1 + d] += wp * v[d];
-                e += 0.5 * wp * v[d] * v[d];
-            }
-            acc[1 + D] += e;
-        }
-    };
-    // pass 1: draw, write weights and positions, reduce N', p', E'
+    Sums sums;
+    sums.zero();
+    // pass 1: draw, write weights and positions, reduce the sample's sums
     if (in_regs) {
 #pragma unroll
         for (int j = 0; j < kReconRegs; ++j) {
@@ -191,7 +302,7 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
                 draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, vr[j], xp);
                 A.w_out[o0 + i] = wp;
                 for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
-                add_moments(vr[j]);
+                sums.add(vr[j], wp);
             }
         }
     } else {
@@ -200,111 +311,88 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
             draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, v, xp);
             A.w_out[o0 + i] = wp;
             for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
-            add_moments(v);
+            sums.add(v, wp);
         }
     }
-    block_sum<NA>(acc, red, par, nwaves);
-    if constexpr (TENSOR) {
-        const double Np = acc[0];
-        double St[NT], Ss[NT], ref_t = 0.0, ref_s = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            ref_t += tg[1 + D + tri_idx<D>(d, d)] / D;
-            ref_s += acc[1 + D + tri_idx<D>(d, d)] / D;
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-#pragma unroll
-            for (int j = i; j < D; ++j) {
-                const int q = tri_idx<D>(i, j);
-                St[q] = tg[1 + D + q] - tg[1 + i] * tg[1 + j] / W;
-                Ss[q] = acc[1 + D + q] - acc[1 + i] * acc[1 + j] / Np;
-            }
-        double Lt[NT], Ls[NT], Li[NT], Am[NT];
-        const bool project = chol_above<D>(St, ref_t, Lt) && chol_above<D>(Ss, ref_s, Ls);
-        double mean_t[D], mean_s[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            mean_t[d] = tg[1 + d] / W;
-            mean_s[d] = acc[1 + d] / Np;
-        }
-        if (project) {
-            tri_inv<D, double>(Ls, Li);
-            tri_mul<D>(Lt, Li, Am);
-        }
-        auto write_t = [&](int64_t i, const double (&v)[D]) {
-            double dv[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) dv[d] = v[d] - mean_s[d];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double t = mean_t[a];
-#pragma unroll
-                for (int b = 0; b <= a; ++b) t += Am[tri_idx<D>(b, a)] * dv[b];
-                A.v_out[(o0 + i) * D + a] = project ? t : v[a];
-            }
-        };
-        if (in_regs) {
-#pragma unroll
-            for (int j = 0; j < kReconRegs; ++j) {
-                const int64_t i = tid + (int64_t)j * nthreads;
-                if (i < n) write_t(i, vr[j]);
-            }
-        } else {
-            for (int64_t i = tid; i < n; i += nthreads) {
-                double v[D], xp[3];
-                draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, 0, v, xp);
-                write_t(i, v);
-            }
-        }
-        if (tid == 0) A.status[c] = (project ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
-        return;
-    }
-    // Lemons: a = sqrt((2 E N' - |P|^2) / (2 E' N' - |p'|^2)), beta = (P - a p') / (a N')
-    double E = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) E += tg[1 + D + tri_idx<D>(d, d)];
-    E *= 0.5;
-    const double Np = acc[0], Ep = acc[1 + D];
-    double P2 = 0.0, pp2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        P2 += tg[1 + d] * tg[1 + d];
-        pp2 += acc[1 + d] * acc[1 + d];
-    }
-    // each bracket is a difference of terms of size 2 E N'; within rounding
-    // of zero (1e-12 of the term) it counts as zero -- the denominator
-    // vanishes exactly when every drawn velocity is the same (n' = 1)
-    const double num = 2.0 * E * Np - P2;
-    const double den = 2.0 * Ep * Np - pp2;
-    const bool project = num > 1e-12 * (2.0 * E * Np) && den > 1e-12 * (2.0 * Ep * Np);
-    double sc = 1.0, beta[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) beta[d] = 0.0;
-    if (project) {
-        sc = sqrt(num / den);
-#pragma unroll
-        for (int d = 0; d < D; ++d) beta[d] = (tg[1 + d] - sc * acc[1 + d]) / (sc * Np);
-    }
-    auto write_v = [&](int64_t i, const double (&v)[D]) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) A.v_out[(o0 + i) * D + d] = project ? sc * (v[d] + beta[d]) : v[d];
-    };
+    block_sum<Sums::NA>(sums.acc, red, par, nwaves);
+    Projection<D, TENSOR> pr;
+    pr.setup(sums.acc, tg);
     // pass 2: projected velocities
     if (in_regs) {
 #pragma unroll
         for (int j = 0; j < kReconRegs; ++j) {
             const int64_t i = tid + (int64_t)j * nthreads;
-            if (i < n) write_v(i, vr[j]);
+            if (i < n) pr.write(vr[j], A.v_out + (o0 + i) * D);
         }
     } else {
         for (int64_t i = tid; i < n; i += nthreads) {
             double v[D], xp[3];
             draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, 0, v, xp);
-            write_v(i, v);
+            pr.write(v, A.v_out + (o0 + i) * D);
         }
     }
-    if (tid == 0) A.status[c] = (project ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
+    if (tid == 0) A.status[c] = (pr.ok ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
+}
+
+// Projection of given particles (v, w) of each cell towards the cell's
+// moments record; v_out may alias v: every thread reads its own particles
+// before the workgroup's reduction and writes the same particles after it.
+template <int D, bool TENSOR>
+__global__ __launch_bounds__(kReconThreads) void k_project(ProjArgs A)
+{
+    using Sums = SampleSums<D, TENSOR>;
+    __shared__ double red[2 * kMaxWaves * Sums::NA];
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    int par = 0;
+    const int64_t o0 = A.off[c];
+    const int64_t n = A.off[c + 1] - o0;
+    if (n <= 0) {
+        if (tid == 0) A.status[c] = 0;
+        return;
+    }
+    const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
+    double vr[kReconRegs][D];
+    Sums sums;
+    sums.zero();
+    auto load = [&](int64_t i, double (&v)[D]) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[d] = A.v[(o0 + i) * D + d];
+    };
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kReconRegs; ++j) {
+            const int64_t i = tid + (int64_t)j * nthreads;
+            if (i < n) {
+                load(i, vr[j]);
+                sums.add(vr[j], A.w[o0 + i]);
+            }
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += nthreads) {
+            double v[D];
+            load(i, v);
+            sums.add(v, A.w[o0 + i]);
+        }
+    }
+    block_sum<Sums::NA>(sums.acc, red, par, nthreads >> 6);
+    Projection<D, TENSOR> pr;
+    pr.setup(sums.acc, A.moments + (size_t)c * nmom(D));
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kReconRegs; ++j) {
+            const int64_t i = tid + (int64_t)j * nthreads;
+            if (i < n) pr.write(vr[j], A.v_out + (o0 + i) * D);
+        }
+    } else {
+        for (int64_t i = tid; i < n; i += nthreads) {
+            double v[D];
+            load(i, v);
+            pr.write(v, A.v_out + (o0 + i) * D);
+        }
+    }
+    if (tid == 0) A.status[c] = pr.ok ? 0 : GM_ST_LEMONS_SKIPPED;
 }
 
 int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st)
@@ -321,6 +409,24 @@ int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st)
             hipLaunchKernelGGL((k_reconstruct<3, true>), grid, block, 0, st, a);
         else
             hipLaunchKernelGGL((k_reconstruct<3, false>), grid, block, 0, st, a);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_project(const ProjArgs& a, int64_t n_cells, hipStream_t st)
+{
+    if (n_cells == 0) return 0;
+    const dim3 grid((unsigned)n_cells), block(kReconThreads);
+    if (a.D == 1) {
+        if (a.tensor)
+            hipLaunchKernelGGL((k_project<1, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_project<1, false>), grid, block, 0, st, a);
+    } else {
+        if (a.tensor)
+            hipLaunchKernelGGL((k_project<3, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_project<3, false>), grid, block, 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -63,3 +63,33 @@ def conservation(rec, c, D):
     Sm = W * sum(w[k] * (unpack(D, rec["sigma"][c, k]) + np.outer(mu[k], mu[k])) for k in range(K))
     scale = np.sqrt(W * np.trace(S))
     return abs(w.sum() - 1.0), np.abs(Pm - P).max() / scale, np.abs(Sm - S).max() / np.trace(S)
+
+
+def spline2(s):
+    """Quadratic B-spline, written out for property checks of GPU outputs."""
+    a = np.abs(s)
+    return np.where(a <= 0.5, 0.75 - a * a, np.where(a <= 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+def deposit_at(x, w, off, dx, nx, cells):
+    """Charge sum_p w_p S2(X_i - X_p) on the given mesh cells of the periodic
+    unit mesh, by brute force over the particles of the neighbouring cells
+    (the definition; a property check of outputs, not a reference)."""
+    n_cells = len(off) - 1
+    ny = n_cells // nx if dx == 2 else 1
+    nxx = nx if dx == 2 else n_cells
+    out = []
+    for i in cells:
+        ix, iy = (i % nxx, i // nxx) if dx == 2 else (i, 0)
+        tot = 0.0
+        for oy in ((-1, 0, 1) if dx == 2 else (0,)):
+            for ox in (-1, 0, 1):
+                j = (((iy + oy) % ny) * nxx + (ix + ox) % nxx) if dx == 2 else (ix + ox) % nxx
+                sl = slice(off[j], off[j + 1])
+                xs = np.asarray(x[sl]).reshape(-1, dx)
+                s = spline2(0.5 - ox - xs[:, 0])
+                if dx == 2:
+                    s = s * spline2(0.5 - oy - xs[:, 1])
+                tot += float((np.asarray(w[sl]) * s).sum())
+        out.append(tot)
+    return np.array(out)

@@ -62,3 +62,18 @@ def test_invalid_arguments_rejected_on_host():
     # reconstruct: bad dx
     assert lib.gm_reconstruct(None, None, None, None, 8, None, None, 1, 3, 4, 0, None, None, None, None, None, 0,
                               None) == -1
+    # projection of given particles: D = 2 is not built, zero cells no-op
+    assert lib.gm_project(None, None, None, None, 4, 2, 0, None, None, None) == -1
+    assert lib.gm_project(None, None, None, None, 4, 3, 2, None, None, None) == -1
+    assert lib.gm_project(None, None, None, None, 0, 3, 1, None, None, None) == 0
+    # Gauss'-law correction: mesh and tolerance checks, workspace sizes
+    assert lib.gm_gauss_workspace(0, 1) == 0 and lib.gm_gauss_workspace(10, 3) == 0
+    n1, n2 = lib.gm_gauss_workspace(4096, 1), lib.gm_gauss_workspace(65536, 2)
+    assert n1 >= 4096 * (2 * 3 + 9) * 8 and n2 >= 65536 * (2 * 9 + 9) * 8
+    assert lib.gm_deposit(None, None, None, 10, 2, 3, None, None, 0, None) == -1  # 3 does not divide 10
+    assert lib.gm_deposit(None, None, None, 10, 1, 10, None, None, 0, None) == -1  # NULL arrays
+    p = ctypes.c_void_p(8)  # never dereferenced: the checks fail first
+    assert lib.gm_deposit(p, p, p, 10, 1, 10, p, None, 0, None) == -3  # no workspace
+    assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 0.0, 50, p, 1 << 20, None, None, None) == -1  # tol
+    assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 1e-12, 0, p, 1 << 20, None, None, None) == -1  # max_iter
+    assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 1e-12, 50, p, 16, None, None, None) == -3  # small workspace

@@ -40,6 +40,16 @@ def _round_bf16(x):
     return torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
 
 
+def _oracle_feature_bits(d):
+    """The oracle's features rounded to BF16: (GPU int16 tensor [n, 128] of
+    bit patterns, the same values as FP64 [n, 105], the oracle's frames).
+    Both sides of a network comparison start from these inputs."""
+    of, ofr = oracle.features(d["v"], d["alpha"], d["cell_off"])
+    b = torch.zeros(of.shape[0], 128, dtype=torch.int16)
+    b[:, :105] = torch.from_numpy(of).to(torch.bfloat16).view(torch.int16)
+    return b.to(dev()), _bf16_bits_to_f64(b[:, :105].numpy()), ofr
+
+
 def _params(seed, scale=0.1):
     rng = np.random.default_rng(seed)
     return {"W1": rng.normal(size=(105, 256)) * scale, "b1": rng.normal(size=256) * 0.05,
@@ -98,14 +108,12 @@ def test_forward_matches_oracle_bf16():
     BF16-rounding forward pass, on 300 rows (ragged 32-row tiles)."""
     api = _api()
     d = _subset(synth.make("weibel_3v"), 300)
-    v, a, off = to_gpu(d)
-    f, _ = api.warm_features(v, a, off)
+    f, X, _ = _oracle_feature_bits(d)
     P = _params(11)
     m = api.WarmStart(16, batch=64, seed=1)
     m.set_params(api.params_to_flat(P))
     Y = m.forward(f)
     torch.cuda.synchronize()
-    X = _bf16_bits_to_f64(f.cpu().numpy())[:, :105]
     _, _, Yo = oracle.mlp_forward(X, P, bf16=True)
     err = _rel(Y.cpu().numpy(), Yo)
     print("forward: relative error %.2e" % err)
@@ -117,8 +125,7 @@ def test_train_step_matches_oracle_gradients_and_adam():
     api = _api()
     B = 200
     d = _subset(synth.make("weibel_3v"), 256)
-    v, a, off = to_gpu(d)
-    f, _ = api.warm_features(v, a, off)
+    f, Xall, _ = _oracle_feature_bits(d)
     rng = np.random.default_rng(8)
     T = np.zeros((256, 160))
     for r in range(256):
@@ -137,7 +144,7 @@ def test_train_step_matches_oracle_gradients_and_adam():
     lr = 1e-3
     m.train_step(f, Tg, torch.from_numpy(idx).to(dev()), lr=lr, lam=1.0, loss_rows=loss_rows)
     grads = api.flat_to_params(m.gradients())
-    X = _bf16_bits_to_f64(f.cpu().numpy())[idx, :105]
+    X = Xall[idx]
     Lo, go = oracle.mlp_loss_backward(X, P, T[idx].astype(np.float32), lam=1.0, bf16=True)
     loss = float(loss_rows.sum().item()) / B
     print("loss gpu %.6f oracle %.6f" % (loss, Lo))
@@ -159,8 +166,9 @@ def test_train_step_matches_oracle_gradients_and_adam():
 def test_decode_matches_oracle():
     api = _api()
     d = _edge_batch()
-    v, a, off = to_gpu(d)
-    _, fr = api.warm_features(v, a, off)
+    _, _, ofr = _oracle_feature_bits(d)
+    fr = torch.from_numpy(ofr).to(dev())
+    off = torch.from_numpy(d["cell_off"]).to(dev())
     n_cells = len(d["cell_off"]) - 1
     rng = np.random.default_rng(9)
     Y = np.zeros((n_cells, 160), np.float32)
@@ -170,7 +178,7 @@ def test_decode_matches_oracle():
         Y[:, 10 * j + 4:10 * j + 10] = rng.normal(size=(n_cells, 6)) * 0.3
     for kmax in (16, 4):
         g = host(api.warm_decode(torch.from_numpy(Y).to(dev()), fr, off, kmax))
-        o = oracle.warm_decode(Y, fr.cpu().numpy(), d["cell_off"], kmax)
+        o = oracle.warm_decode(Y, ofr, d["cell_off"], kmax)
         np.testing.assert_array_equal(g["K"], o["K"])
         for k in ("omega", "mu", "sigma"):
             np.testing.assert_allclose(g[k], o[k], rtol=1e-12, atol=1e-15)
@@ -218,8 +226,14 @@ def test_pipeline_warm_compress_matches_oracle():
     m = api.WarmStart(16, batch=64, seed=1)
     m.set_params(api.params_to_flat(P))
     gi = m.initial_mixtures(v, a, off)
-    init = host(gi)
-    assert (init["K"] == 2).all()
+    hg = host(gi)
+    # the oracle's own chain: features, BF16 forward pass, decode
+    _, X, ofr = _oracle_feature_bits(d)
+    _, _, Yo = oracle.mlp_forward(X, P, bf16=True)
+    init = oracle.warm_decode(Yo.astype(np.float32), ofr, d["cell_off"], 16)
+    assert (init["K"] == 2).all() and (hg["K"] == 2).all()
+    for k in ("omega", "mu", "sigma"):
+        np.testing.assert_allclose(hg[k], init[k], rtol=1e-6, atol=1e-9)
     g = host(api.compress(v, a, off, 16, seed=4, max_sweeps=150, init=gi))
     o = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=16, seed=4, max_sweeps=150, init=init)
     fb_g, fb_o = (g["status"] & FALLBACK) != 0, (o["status"] & FALLBACK) != 0

@@ -1,7 +1,8 @@
 """Pins of the oracle's Gauss'-law weight correction (Sec. 2.4.1):
 
 * the quadratic B-spline's closed-form values and its partition of unity;
-* the deposit conserves total charge (1D and 2D periodic meshes);
+* the deposit conserves total charge (1D and 2D periodic meshes) and
+  equals a per-mesh-cell brute-force sum written separately;
 * every column of the mass matrix is the deposit's response to a unit
   weight change of the particles of that cell (brute force), and sums to the
   cell's particle count;
@@ -17,12 +18,24 @@ import oracle
 from oracle import gauss
 from paper_2007_12273_amd import synth
 
+from gpu_util import deposit_at
+
 
 def test_s2_values_and_partition_of_unity():
     assert gauss.s2(0.0) == 0.75 and gauss.s2(0.5) == 0.5 and gauss.s2(1.0) == 0.125
     assert gauss.s2(1.5) == 0.0 and gauss.s2(-1.0) == 0.125 and gauss.s2(2.0) == 0.0
     s = np.linspace(-0.5, 0.5, 101)
     np.testing.assert_allclose(gauss.s2(s - 1) + gauss.s2(s) + gauss.s2(s + 1), 1.0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("dx,n_cells,nx", [(1, 17, 17), (2, 30, 6), (1, 2, 2), (2, 4, 2), (2, 3, 1)])
+def test_deposit_equals_brute_force_per_cell(dx, n_cells, nx):
+    """The vectorised deposit against a per-mesh-cell sum over the particles
+    of the neighbouring cells, written separately (also on meshes narrower
+    than the stencil, where a cell is its own neighbour)."""
+    x, w, off = _layout(dx, 9, n_cells, 1, 20)
+    D = gauss.deposit(x, w, off, dx, nx)
+    np.testing.assert_allclose(D, deposit_at(x, w, off, dx, nx, range(n_cells)), rtol=0, atol=1e-13)
 
 
 def _layout(dx, seed, n_cells, lo=5, hi=40):
