@@ -29,6 +29,7 @@ STATUS = {
 }
 MODE_STANDARD_EM = 1
 MODE_NO_FINISH = 2
+MODE_OUTER_K = 4
 
 
 def build(force=False):

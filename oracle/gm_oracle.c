@@ -42,6 +42,8 @@
 /* oracle mode flags */
 #define ORC_MODE_STANDARD_EM 1 /* joint E-step, MLE weights, no annihilation */
 #define ORC_MODE_NO_FINISH 2   /* report the penalised state, skip the unpenalised step */
+#define ORC_MODE_OUTER_K 4     /* outer search over K: after each converged run remove the
+                                  least probable component and run again, keep the best */
 
 static const double LN_2PI = 1.8378770664093454835606594728112;
 static const double TWO_PI = 6.283185307179586476925286766559;
@@ -533,75 +535,108 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
             free(perm);
         }
 
-        /* O4-O6: component-wise adaptive EM sweeps (Sec. 2.3 steps 1-4) */
+        /* O4-O6: component-wise adaptive EM sweeps (Sec. 2.3 steps 1-4).
+         * With the outer search over K (the component-wise algorithm the
+         * paper cites for its penalised likelihood, Sec. 1): after every
+         * converged run the state is kept if its penalised L is the best so
+         * far, the least probable component (smallest weight, lowest slot
+         * on ties) is removed, the weights renormalised, and the sweeps run
+         * again, down to K = 1; the best state is the result.  Each run
+         * counts its own sweeps for the stop test and the cap. */
         const int standard = (J->mode & ORC_MODE_STANDARD_EM) != 0;
+        const int outer = (J->mode & ORC_MODE_OUTER_K) != 0 && fixed <= 0 && !standard;
         const int cap_sweeps = fixed > 0 ? fixed : J->max_sweeps;
-        double L_prev = 0.0;
         const double half_T = 0.5 * T;
-        for (s = 1; s <= cap_sweeps; ++s) {
-            int annihilated = 0;
-            if (standard) {
-                /* plain EM: joint E-step, then every component's M-step with
-                 * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
-                double* gk = g;
-                mixture next = m;
-                double gp[ORC_MAXK];
-                for (int p = 0; p < n; ++p) {
-                    particle_responsibilities(D, &m, x + (size_t)p * D, a[p], gp);
-                    for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = gp[k];
-                }
-                for (int k = 0; k < m.K; ++k) {
-                    double Nk = 0.0;
-                    for (int p = 0; p < n; ++p) Nk += gk[(size_t)k * n + p];
-                    mean_cov(D, n, x, gk + (size_t)k * n, Nk, next.mu[k], next.S[k]);
-                    next.w[k] = Nk / N;
-                    if (factor_component(D, &next, k, trC)) status |= ORC_COV_FLOOR;
-                }
-                visits += m.K;
-                m = next;
-            } else {
-                int k = 0;
-                while (k < m.K) {
-                    /* step 1: E-step for component k with the current parameters */
-                    responsibilities(D, &m, k, n, x, a, g);
-                    double Nk = 0.0;
-                    for (int p = 0; p < n; ++p) Nk += g[p];
-                    ++visits;
-                    if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
-                    /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
-                    if (Nk - half_T <= 0.0) {
-                        remove_component(&m, k);
-                        renormalise(&m);
-                        annihilated = 1;
-                        continue;
+        mixture best;
+        double L_best = -INFINITY;
+        int have_best = 0, s_total = 0;
+        for (;;) {
+            double L_prev = 0.0;
+            for (s = 1; s <= cap_sweeps; ++s) {
+                int annihilated = 0;
+                if (standard) {
+                    /* plain EM: joint E-step, then every component's M-step with
+                     * w_k = N_k / N (eq. omegak-mle); used only as a test mode */
+                    double* gk = g;
+                    mixture next = m;
+                    double gp[ORC_MAXK];
+                    for (int p = 0; p < n; ++p) {
+                        particle_responsibilities(D, &m, x + (size_t)p * D, a[p], gp);
+                        for (int k = 0; k < m.K; ++k) gk[(size_t)k * n + p] = gp[k];
                     }
-                    mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
-                    /* eq. (omegak) with K the current number of live components */
-                    m.w[k] = (Nk - half_T) / (N - half_T * m.K);
-                    /* step 3: renormalise */
-                    renormalise(&m);
-                    if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
-                    ++k;
+                    for (int k = 0; k < m.K; ++k) {
+                        double Nk = 0.0;
+                        for (int p = 0; p < n; ++p) Nk += gk[(size_t)k * n + p];
+                        mean_cov(D, n, x, gk + (size_t)k * n, Nk, next.mu[k], next.S[k]);
+                        next.w[k] = Nk / N;
+                        if (factor_component(D, &next, k, trC)) status |= ORC_COV_FLOOR;
+                    }
+                    visits += m.K;
+                    m = next;
+                } else {
+                    int k = 0;
+                    while (k < m.K) {
+                        /* step 1: E-step for component k with the current parameters */
+                        responsibilities(D, &m, k, n, x, a, g);
+                        double Nk = 0.0;
+                        for (int p = 0; p < n; ++p) Nk += g[p];
+                        ++visits;
+                        if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
+                        /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
+                        if (Nk - half_T <= 0.0) {
+                            remove_component(&m, k);
+                            renormalise(&m);
+                            annihilated = 1;
+                            continue;
+                        }
+                        mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
+                        /* eq. (omegak) with K the current number of live components */
+                        m.w[k] = (Nk - half_T) / (N - half_T * m.K);
+                        /* step 3: renormalise */
+                        renormalise(&m);
+                        if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+                        ++k;
+                    }
                 }
-            }
-            /* step 4: monitor the penalised log-likelihood */
-            L_s = penalised_L(D, T, &m, n, x, a, N);
-            if (J->L_trace) J->L_trace[(size_t)c * J->max_sweeps + (s - 1)] = L_s;
-            if (J->K_trace) J->K_trace[(size_t)c * J->max_sweeps + (s - 1)] = m.K;
-            if (fixed > 0) {
-                if (s == fixed) break;
+                /* step 4: monitor the penalised log-likelihood */
+                L_s = penalised_L(D, T, &m, n, x, a, N);
+                if (s_total + s <= J->max_sweeps) {
+                    if (J->L_trace) J->L_trace[(size_t)c * J->max_sweeps + (s_total + s - 1)] = L_s;
+                    if (J->K_trace) J->K_trace[(size_t)c * J->max_sweeps + (s_total + s - 1)] = m.K;
+                }
+                if (fixed > 0) {
+                    if (s == fixed) break;
+                    L_prev = L_s;
+                    continue;
+                }
+                if (!isfinite(L_s)) break; /* eq. (lnL-GM) undefined: no further sweep can help */
+                if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
+                if (s == J->max_sweeps) {
+                    status |= ORC_MAXSWEEPS;
+                    break;
+                }
                 L_prev = L_s;
-                continue;
             }
-            if (!isfinite(L_s)) break; /* eq. (lnL-GM) undefined: no further sweep can help */
-            if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= J->tol * fabs(L_s)) break;
-            if (s == J->max_sweeps) {
-                status |= ORC_MAXSWEEPS;
-                break;
+            if (s > cap_sweeps) s = cap_sweeps;
+            s_total += s;
+            if (!outer) break;
+            if (!have_best || L_s > L_best) {
+                best = m;
+                L_best = L_s;
+                have_best = 1;
             }
-            L_prev = L_s;
+            if (m.K <= 1 || !isfinite(L_s)) break;
+            int kmin = 0;
+            for (int k = 1; k < m.K; ++k)
+                if (m.w[k] < m.w[kmin]) kmin = k;
+            remove_component(&m, kmin);
+            renormalise(&m);
         }
-        if (s > cap_sweeps) s = cap_sweeps;
+        if (outer && have_best) {
+            m = best;
+            L_s = L_best;
+        }
+        s = s_total;
         if (!have_init || fixed > 0 || L_s >= L_one - 1e-5 * fabs(L_one)) break;
         /* rejected warm start: cold start, flags of the cold fit only */
         have_init = 0;

@@ -13,7 +13,9 @@ mathematics fix, independent of the oracle's own code:
 * annihilation exactly when N_k <= T/2;
 * exact conservation of mass, mean and second-moment tensor after the
   unpenalised finish, for arbitrary mixtures (Sec. 2.3.1);
-* recovery of well-separated mixtures.
+* recovery of well-separated mixtures;
+* the outer search over K against the single-Gaussian closed form: never
+  below it, equal to it where it returns K = 1, never below the single pass.
 """
 import numpy as np
 import pytest
@@ -470,3 +472,36 @@ def test_stop_rule_resolution():
     assert len(errs) >= 12
     assert max(lerr) < 1e-5
     assert np.median(errs) > 1e-4 and errs.max() > 1e-3
+
+
+def _one_gaussian_cells(seed, n_cells=12, n=2000):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(n_cells, 3, 3)) * 0.3 + np.eye(3)
+    v = np.concatenate([rng.normal(size=(n, 3)) @ A[c].T + rng.normal(size=3) for c in range(n_cells)])
+    off = np.arange(n_cells + 1, dtype=np.int64) * n
+    return v, np.ones(len(v)), off
+
+
+@pytest.mark.parametrize("kmax", [2, 8])
+def test_outer_k_search_on_single_gaussian_cells(kmax):
+    """The outer search over K ends at K = 1 (its last run) unless a larger
+    K scored a higher penalised L: so its L is never below the K = 1 closed
+    form N (-D/2 ln 2 pi - 1/2 ln det C - D/2) - (T/2) ln N, equals it
+    wherever it returns K = 1, and is never below the plain single pass
+    (its first run) nor has more components."""
+    v, a, off = _one_gaussian_cells(7)
+    plain = oracle.compress(v, a, off, kmax=kmax, seed=5)
+    outer = oracle.compress(v, a, off, kmax=kmax, seed=5, mode=oracle.MODE_OUTER_K)
+    closed = np.array([2000 * (-1.5 * np.log(2 * np.pi) - 0.5 * np.log(np.linalg.det(np.cov(
+        v[off[c]:off[c + 1]].T, bias=True))) - 1.5) - 4.5 * np.log(2000) for c in range(len(off) - 1)])
+    assert (outer["L_pen"] >= closed - 1e-9 * np.abs(closed)).all()
+    one = outer["K"] == 1
+    np.testing.assert_allclose(outer["L_pen"][one], closed[one], rtol=1e-10)
+    assert (outer["L_pen"] >= plain["L_pen"]).all() and (outer["K"] <= plain["K"]).all()
+    assert one.mean() >= 0.75
+    # where the single pass kept a second component that the penalty does
+    # not pay for, the search finds the better single Gaussian
+    worse = (plain["K"] > 1) & (plain["L_pen"] < closed)
+    assert worse.any() and (outer["K"][worse] == 1).all()
+    # one more run, of at least two sweeps, per removed component
+    assert (outer["sweeps"] >= plain["sweeps"] + 2 * (plain["K"] - 1)).all()
