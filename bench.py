@@ -92,6 +92,7 @@ def parse():
     p.add_argument("--train-sets", type=int, default=16, help="training batches of cells (seeds 5000+i)")
     p.add_argument("--epochs", type=int, default=50)
     p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
+    p.add_argument("--no-outer", action="store_true", help="skip the outer-search-over-K measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     p.add_argument("--no-tune", action="store_true", help="keep the built-in EM launch plans (no gm_autotune)")
@@ -213,6 +214,22 @@ def phase_times(fn, reps, api, torch):
             ph["warm_init"].append(t)
     api.profile_enable(False)
     return {k: float(np.mean(x)) for k, x in ph.items() if x}
+
+
+def outer_k_search(v, alpha, off, D, kmax, W, cold, reps, api, torch):
+    """The cold compress with the outer search over K (gm_opts.outer_k),
+    against the single pass of the same start: time, K, penalised L."""
+    import numpy as np
+    n_cells = off.numel() - 1
+    comp = api.Compressor(n_cells, D, kmax, device=off.device, seed=W["init_seed"], outer_k=True)
+    ms = time_steps(lambda: comp(v, alpha, off), reps, 1, torch)
+    o = {k: t.cpu().numpy() for k, t in comp.out.as_dict().items()}
+    ok = np.isfinite(o["L_pen"]) & np.isfinite(cold["L_pen"])
+    gain = o["L_pen"][ok] - cold["L_pen"][ok]
+    return {"ms_per_compress": ms, "mean_K": float(o["K"].mean()), "mean_K_single_pass": float(cold["K"].mean()),
+            "fewer_components_frac": float((o["K"] < cold["K"]).mean()),
+            "L_gain_nats_mean": float(gain.mean()), "L_gain_nats_max": float(gain.max()),
+            "sweeps_ratio": float(o["sweeps"].sum() / max(1, cold["sweeps"].sum()))}
 
 
 def restart_chain(data, W, off, comp, recon, reps, api, torch):
@@ -467,6 +484,9 @@ def main():
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
     }
     line.update(line_extra)
+    if not args.no_outer:
+        line["outer_k_search"] = outer_k_search(v, alpha, off, D, kmax, W, cold, max(1, min(args.steps, 3)), api,
+                                                torch)
     if "x" in data:  # workloads with particle positions
         line["restart_chain"] = restart_chain(data, W, off, comp_c, recon, max(3, min(args.steps, 10)), api, torch)
     if graph:

@@ -74,7 +74,16 @@ typedef struct gm_opts {
                              without annihilation (default 1e-7) */
     uint64_t seed;        /* seed of the cold-start particle choice */
     int32_t estep_fp64;   /* 0: EM iterations in FP32 (default); 1: in FP64 */
-    int32_t reserved;     /* must be 0 */
+    int32_t outer_k;      /* 0: one run of the sweeps (the paper's algorithm, default);
+                             1: outer search over K: after every converged run keep
+                             the state if its penalised L is the best so far, remove
+                             the least probable component (smallest weight, lowest
+                             slot on ties) and run again, down to K = 1; the best
+                             state is the result (the component-wise algorithm the
+                             paper cites for its penalised likelihood, Sec. 1).
+                             Every run counts its own sweeps for the stop test and
+                             the cap; sweeps and visits report the totals.  Ignored
+                             in replay mode (fixed_sweeps > 0). */
 } gm_opts;
 
 /* Fill *o with the defaults above for the given D and kmax. */

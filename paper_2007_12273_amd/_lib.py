@@ -27,7 +27,7 @@ class GmOpts(ctypes.Structure):
     _fields_ = [
         ("D", ctypes.c_int32), ("kmax", ctypes.c_int32), ("n_min", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32), ("tol_rel", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("estep_fp64", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("estep_fp64", ctypes.c_int32), ("outer_k", ctypes.c_int32),
     ]
 
 

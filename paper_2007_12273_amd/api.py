@@ -36,7 +36,7 @@ def _need(t, dtype, name):
         raise ValueError("%s must be contiguous" % name)
 
 
-def make_opts(D, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False):
+def make_opts(D, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False, outer_k=False):
     o = GmOpts()
     _lib.load().gm_opts_default(ctypes.byref(o), D, kmax)
     o.n_min = n_min
@@ -44,6 +44,7 @@ def make_opts(D, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False):
     o.tol_rel = tol
     o.seed = seed
     o.estep_fp64 = 1 if fp64 else 0
+    o.outer_k = 1 if outer_k else 0
     return o
 
 
@@ -143,13 +144,14 @@ class Compressor:
 
 
 def compress(v, alpha, cell_off, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False, fixed_sweeps=None,
-             init=None, stream=None):
+             init=None, stream=None, outer_k=False):
     """Adaptive EM-GM compress of every cell.  Returns a dict of GPU tensors
-    (K, omega, mu, sigma, moments, L_pen, L_final, sweeps, status, visits)."""
+    (K, omega, mu, sigma, moments, L_pen, L_final, sweeps, status, visits).
+    outer_k: outer search over K (gm_opts.outer_k)."""
     D = 1 if v.dim() == 1 else v.shape[1]
     n_cells = cell_off.numel() - 1
     c = Compressor(n_cells, D, kmax, device=v.device, n_min=n_min, max_sweeps=max_sweeps, tol=tol, seed=seed,
-                   fp64=fp64)
+                   fp64=fp64, outer_k=outer_k)
     return c(v.contiguous(), alpha, cell_off, fixed_sweeps=fixed_sweeps, init=init, stream=stream).as_dict()
 
 

@@ -189,7 +189,7 @@ bool valid_opts(const gm_opts* o)
     if (o->max_sweeps < 1) return false;
     if (!(o->tol_rel >= 0.0)) return false;
     if (o->estep_fp64 != 0 && o->estep_fp64 != 1) return false;
-    if (o->reserved != 0) return false;
+    if (o->outer_k != 0 && o->outer_k != 1) return false;
     return true;
 }
 
@@ -208,7 +208,7 @@ void gm_opts_default(gm_opts* o, int32_t D, int32_t kmax)
     o->tol_rel = 1e-7;
     o->seed = 0;
     o->estep_fp64 = 0;
-    o->reserved = 0;
+    o->outer_k = 0;
 }
 
 size_t gm_compress_workspace(int64_t n_cells, const gm_opts* o)
@@ -248,6 +248,7 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
     a.max_sweeps = o->max_sweeps;
     a.tol = o->tol_rel;
     a.seed = o->seed;
+    a.outer = o->outer_k;
     a.fixed = fixed_sweeps;
     if (init && init->K) a.init = *init;
     a.out = *out;
@@ -304,6 +305,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     a.max_sweeps = o->max_sweeps;
     a.tol = o->tol_rel;
     a.seed = o->seed;
+    a.outer = o->outer_k;
     a.fixed = nullptr;
     const bool warm = init && init->K;
     if (warm) a.init = *init;

@@ -70,6 +70,7 @@ struct CompressArgs {
     int32_t bucket;
     int32_t nwaves;
     int32_t kmax, n_min, max_sweeps;
+    int32_t outer;           // 1: outer search over K (gm_opts.outer_k)
     double tol;
     uint64_t seed;
     const int32_t* fixed;    // nullable
@@ -471,6 +472,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
 
     __shared__ CompressArgs A;   // arguments read where they are used, not pinned in SGPRs
     __shared__ CompState<R, D> compw[kEmMaxWaves][KMAX];
+    __shared__ CompState<R, D> bestc[KMAX];  // best state of the outer search over K
     __shared__ double red_d[2 * kMaxWaves * 2];
     __shared__ R red_r[2 * kEmMaxWaves * NS];  // zero where no wave writes (em_block_sum)
     __shared__ int s_idx;
@@ -589,332 +591,375 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
             G = R(0);
             for (int j = 0; j < K; ++j) G += comp[j].u;
 
-            // ---------------- initial density terms ------------------------------
-            if constexpr (STORE_E) {
-                for (int j = 0; j < K; ++j) {
-                    const CompState<R, D> cj = comp[j];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
-                }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    R mx = e[p][0];
-#pragma unroll
-                    for (int j = 1; j < KMAX; ++j)
-                        if (j < K) mx = fmax(mx, e[p][j]);
-                    ref[p] = mx;
-#pragma unroll
-                    for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
-                    Sden[p] = resum(e[p]);
-                }
-            } else {
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    R mx = R(-1e30);
-                    for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
-                    R s = R(0);
-                    for (int j = 0; j < K; ++j) s += fast_exp2(log2_term<R, D>(comp[j], x[p]) - mx);
-                    ref[p] = mx;
-                    Sden[p] = s;
-                }
-            }
-
-            // ---------------- sweeps ---------------------------------------------
-            const int max_sweeps = A.max_sweeps;
-            const double tol = A.tol;
-            const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
-            int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
-            uint32_t alive = (1u << K) - 1u;
-            // A particle whose density sum falls far below its reference (every
-            // live component now far from it, e.g. after the one that covered
-            // it was annihilated or moved away) gets its terms recomputed in
-            // log2 space about their own maximum, as a log-sum-exp would, so
-            // that no term underflows to zero.
-            const R rebase_below = R(9.094947017729282e-13);  // 2^-40
-            auto rebase_store = [&](VecK& ep, const R (&xp)[D], R& refp) -> R {
-                R mx = R(-INFINITY);
-#pragma unroll
-                for (int j = 0; j < KMAX; ++j) {
-                    const bool live = j < Kslots && ((alive >> j) & 1u);
-                    const R t = live ? log2_term<R, D>(comp[j], xp) : R(-INFINITY);
-                    ep[j] = t;
-                    mx = fmax(mx, t);
-                }
-                if (!(mx > R(-INFINITY))) return R(0);
-#pragma unroll
-                for (int j = 0; j < KMAX; ++j)
-                    ep[j] = (j < Kslots && ((alive >> j) & 1u)) ? fast_exp2(ep[j] - mx) : R(0);
-                refp = mx;
-                return resum(ep);
-            };
-            auto rebase_sum = [&](const R (&xp)[D], R& refp) -> R {
-                R mx = R(-INFINITY);
-                for (int j = 0; j < Kslots; ++j)
-                    if ((alive >> j) & 1u) mx = fmax(mx, log2_term<R, D>(comp[j], xp));
-                if (!(mx > R(-INFINITY))) return R(0);
-                R sum = R(0);
-                for (int j = 0; j < Kslots; ++j)
-                    if ((alive >> j) & 1u) sum += fast_exp2(log2_term<R, D>(comp[j], xp) - mx);
-                refp = mx;
-                return sum;
-            };
-            // Particles flagged in `low` lost most of their density in an
-            // update (the running sum may have cancelled): re-sum their terms
-            // exactly, and rebase those whose sum is still tiny.  Particles
-            // flagged in `big` got a term more than 2^64 above their reference
-            // (a component moved onto a particle that had been rebased far
-            // down): rebase them.  The branch is wave-uniform and rarely taken.
-            auto repair_store = [&](uint32_t low, uint32_t big) {
+            // Runs of the outer search over K (a single run unless A.outer):
+            // after every converged run the state is kept if its penalised L
+            // is the best so far, the least probable component is removed
+            // and the sweeps run again, down to K = 1.
+            const bool outer = A.outer != 0 && fixed <= 0;
+            double L_best = -INFINITY;
+            int K_best = 0, s_total = 0;
+            R G_best = R(0);
+            for (;;) {
+                // ---------------- initial density terms ------------------------------
                 if constexpr (STORE_E) {
-                    if (__builtin_amdgcn_ballot_w64((low | big) != 0) == 0) return;
+                    for (int j = 0; j < K; ++j) {
+                        const CompState<R, D> cj = comp[j];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) e[p][j] = log2_term<R, D>(cj, x[p]);
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        if ((big >> p) & 1u) {
-                            Sden[p] = rebase_store(e[p], x[p], ref[p]);
-                        } else if ((low >> p) & 1u) {
-                            Sden[p] = resum(e[p]);
-                            if (!(Sden[p] > rebase_below)) Sden[p] = rebase_store(e[p], x[p], ref[p]);
-                        }
+                        R mx = e[p][0];
+#pragma unroll
+                        for (int j = 1; j < KMAX; ++j)
+                            if (j < K) mx = fmax(mx, e[p][j]);
+                        ref[p] = mx;
+#pragma unroll
+                        for (int j = 0; j < KMAX; ++j) e[p][j] = (j < K) ? fast_exp2(e[p][j] - mx) : R(0);
+                        Sden[p] = resum(e[p]);
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        R mx = R(-1e30);
+                        for (int j = 0; j < K; ++j) mx = fmax(mx, log2_term<R, D>(comp[j], x[p]));
+                        R s = R(0);
+                        for (int j = 0; j < K; ++j) s += fast_exp2(log2_term<R, D>(comp[j], x[p]) - mx);
+                        ref[p] = mx;
+                        Sden[p] = s;
                     }
                 }
-            };
 
-            double L_prev = 0.0;
-            for (s = 1; s <= cap_sweeps; ++s) {
-                bool annihilated = false;
-                for (int k = 0; k < Kslots; ++k) {
-                    if (!((alive >> k) & 1u)) continue;
-                    ++visits;
-                    R ckmu[D];
+                // ---------------- sweeps ---------------------------------------------
+                const int max_sweeps = A.max_sweeps;
+                const double tol = A.tol;
+                const int cap_sweeps = fixed > 0 ? fixed : max_sweeps;
+                int Kslots = K;  // slots 0..Kslots-1 hold components; some may die within a sweep
+                uint32_t alive = (1u << K) - 1u;
+                // A particle whose density sum falls far below its reference (every
+                // live component now far from it, e.g. after the one that covered
+                // it was annihilated or moved away) gets its terms recomputed in
+                // log2 space about their own maximum, as a log-sum-exp would, so
+                // that no term underflows to zero.
+                const R rebase_below = R(9.094947017729282e-13);  // 2^-40
+                auto rebase_store = [&](VecK& ep, const R (&xp)[D], R& refp) -> R {
+                    R mx = R(-INFINITY);
 #pragma unroll
-                    for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
-                    const R cku = comp[k].u;
-                    // E-step of k with the current parameters of every component,
-                    // and the M-step sums about the current mean of k
-                    R sums[NS];
+                    for (int j = 0; j < KMAX; ++j) {
+                        const bool live = j < Kslots && ((alive >> j) & 1u);
+                        const R t = live ? log2_term<R, D>(comp[j], xp) : R(-INFINITY);
+                        ep[j] = t;
+                        mx = fmax(mx, t);
+                    }
+                    if (!(mx > R(-INFINITY))) return R(0);
 #pragma unroll
-                    for (int t = 0; t < NS; ++t) sums[t] = R(0);
-                    [[maybe_unused]] R eold[STORE_E ? 1 : P];
-                    auto accumulate = [&](int p, R ek, R den) {
-                        const R inv = den > R(0) ? fast_rcp(den) : R(0);
-                        const R g = a[p] * ek * inv;
-                        R d[D];
-#pragma unroll
-                        for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
-                        sums[0] += g;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) {
-                            const R gd = g * d[i];
-                            sums[1 + i] += gd;
-#pragma unroll
-                            for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
-                        }
-                    };
+                    for (int j = 0; j < KMAX; ++j)
+                        ep[j] = (j < Kslots && ((alive >> j) & 1u)) ? fast_exp2(ep[j] - mx) : R(0);
+                    refp = mx;
+                    return resum(ep);
+                };
+                auto rebase_sum = [&](const R (&xp)[D], R& refp) -> R {
+                    R mx = R(-INFINITY);
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) mx = fmax(mx, log2_term<R, D>(comp[j], xp));
+                    if (!(mx > R(-INFINITY))) return R(0);
+                    R sum = R(0);
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) sum += fast_exp2(log2_term<R, D>(comp[j], xp) - mx);
+                    refp = mx;
+                    return sum;
+                };
+                // Particles flagged in `low` lost most of their density in an
+                // update (the running sum may have cancelled): re-sum their terms
+                // exactly, and rebase those whose sum is still tiny.  Particles
+                // flagged in `big` got a term more than 2^64 above their reference
+                // (a component moved onto a particle that had been rebased far
+                // down): rebase them.  The branch is wave-uniform and rarely taken.
+                auto repair_store = [&](uint32_t low, uint32_t big) {
                     if constexpr (STORE_E) {
-#pragma unroll
-                        for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
-                    } else {
-                        const CompState<R, D> ck = comp[k];
+                        if (__builtin_amdgcn_ballot_w64((low | big) != 0) == 0) return;
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
-                            accumulate(p, eold[p], Sden[p]);
+                            if ((big >> p) & 1u) {
+                                Sden[p] = rebase_store(e[p], x[p], ref[p]);
+                            } else if ((low >> p) & 1u) {
+                                Sden[p] = resum(e[p]);
+                                if (!(Sden[p] > rebase_below)) Sden[p] = rebase_store(e[p], x[p], ref[p]);
+                            }
                         }
                     }
-                    em_block_sum<NS, kEmMaxWaves>(sums, red_r, par_r, nwaves);
-                    const R Nk = sums[0];
-                    const R NkT = Nk - (R)halfT;
-                    if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
-                    if (NkT <= R(0)) {
-                        // annihilate k (eq. omegak); the weights renormalise through G
-                        alive &= ~(1u << k);
-                        G -= cku;
-                        --K;
-                        annihilated = true;
+                };
+
+                double L_prev = 0.0;
+                for (s = 1; s <= cap_sweeps; ++s) {
+                    bool annihilated = false;
+                    for (int k = 0; k < Kslots; ++k) {
+                        if (!((alive >> k) & 1u)) continue;
+                        ++visits;
+                        R ckmu[D];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) ckmu[i] = comp[k].mu[i];
+                        const R cku = comp[k].u;
+                        // E-step of k with the current parameters of every component,
+                        // and the M-step sums about the current mean of k
+                        R sums[NS];
+#pragma unroll
+                        for (int t = 0; t < NS; ++t) sums[t] = R(0);
+                        [[maybe_unused]] R eold[STORE_E ? 1 : P];
+                        auto accumulate = [&](int p, R ek, R den) {
+                            const R inv = den > R(0) ? fast_rcp(den) : R(0);
+                            const R g = a[p] * ek * inv;
+                            R d[D];
+#pragma unroll
+                            for (int i = 0; i < D; ++i) d[i] = x[p][i] - ckmu[i];
+                            sums[0] += g;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) {
+                                const R gd = g * d[i];
+                                sums[1 + i] += gd;
+#pragma unroll
+                                for (int j = i; j < D; ++j) sums[1 + D + tri_idx<D>(i, j)] += gd * d[j];
+                            }
+                        };
                         if constexpr (STORE_E) {
-                            uint32_t low = 0;
+#pragma unroll
+                            for (int p = 0; p < P; ++p) accumulate(p, e[p][k], Sden[p]);
+                        } else {
+                            const CompState<R, D> ck = comp[k];
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
+                                eold[p] = fast_exp2(fmin(log2_term<R, D>(ck, x[p]) - ref[p], R(64)));
+                                accumulate(p, eold[p], Sden[p]);
+                            }
+                        }
+                        em_block_sum<NS, kEmMaxWaves>(sums, red_r, par_r, nwaves);
+                        const R Nk = sums[0];
+                        const R NkT = Nk - (R)halfT;
+                        if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
+                        if (NkT <= R(0)) {
+                            // annihilate k (eq. omegak); the weights renormalise through G
+                            alive &= ~(1u << k);
+                            G -= cku;
+                            --K;
+                            annihilated = true;
+                            if constexpr (STORE_E) {
+                                uint32_t low = 0;
+#pragma unroll
+                                for (int p = 0; p < P; ++p) {
+                                    const R s_old = Sden[p];
+                                    const R s_new = s_old - e[p][k];
+                                    e[p][k] = R(0);
+                                    Sden[p] = s_new;
+                                    low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
+                                }
+                                repair_store(low, 0u);
+                            } else {
+#pragma unroll
+                                for (int p = 0; p < P; ++p) {
+                                    const R s_old = Sden[p];
+                                    R s_new = s_old - eold[p];
+                                    if (!(s_new > R(1e-4) * s_old)) {
+                                        s_new = R(0);
+                                        for (int j = 0; j < Kslots; ++j)
+                                            if ((alive >> j) & 1u)
+                                                s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
+                                    }
+                                    Sden[p] = (s_new > rebase_below) ? s_new : rebase_sum(x[p], ref[p]);
+                                }
+                            }
+                            continue;
+                        }
+                        // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
+                        CompState<R, D> cn;
+                        const R invN = m_rcp(Nk);
+                        R dl[D];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            dl[i] = sums[1 + i] * invN;
+                            cn.mu[i] = ckmu[i] + dl[i];
+                        }
+#pragma unroll
+                        for (int i = 0; i < D; ++i)
+#pragma unroll
+                            for (int j = i; j < D; ++j)
+                                cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
+                        const R wk = NkT * m_rcp((R)(N - halfT * K));
+                        const R unew = wk * G;
+                        G = G - cku + unew;
+                        cn.u = unew;
+                        if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
+                        if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
+                        if constexpr (STORE_E) {
+                            uint32_t low = 0, big = 0;
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
+                                const R enew = fast_exp2(fmin(dt, R(64)));
                                 const R s_old = Sden[p];
-                                const R s_new = s_old - e[p][k];
-                                e[p][k] = R(0);
+                                const R s_new = s_old - e[p][k] + enew;
+                                e[p][k] = enew;
                                 Sden[p] = s_new;
                                 low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
+                                big |= (uint32_t)(dt > R(64)) << p;
                             }
-                            repair_store(low, 0u);
+                            repair_store(low, big);
                         } else {
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
+                                const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
+                                const R enew = fast_exp2(fmin(dt, R(64)));
                                 const R s_old = Sden[p];
-                                R s_new = s_old - eold[p];
+                                R s_new = s_old - eold[p] + enew;
                                 if (!(s_new > R(1e-4) * s_old)) {
-                                    s_new = R(0);
+                                    // the particle lost most of its density: re-sum exactly
+                                    s_new = enew;
                                     for (int j = 0; j < Kslots; ++j)
-                                        if ((alive >> j) & 1u)
+                                        if (j != k && ((alive >> j) & 1u))
                                             s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
                                 }
-                                Sden[p] = (s_new > rebase_below) ? s_new : rebase_sum(x[p], ref[p]);
+                                Sden[p] = (s_new > rebase_below && !(dt > R(64))) ? s_new : rebase_sum(x[p], ref[p]);
                             }
                         }
-                        continue;
                     }
-                    // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
-                    CompState<R, D> cn;
-                    const R invN = m_rcp(Nk);
-                    R dl[D];
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        dl[i] = sums[1 + i] * invN;
-                        cn.mu[i] = ckmu[i] + dl[i];
-                    }
-#pragma unroll
-                    for (int i = 0; i < D; ++i)
-#pragma unroll
-                        for (int j = i; j < D; ++j)
-                            cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
-                    const R wk = NkT * m_rcp((R)(N - halfT * K));
-                    const R unew = wk * G;
-                    G = G - cku + unew;
-                    cn.u = unew;
-                    if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
-                    if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
-                    if constexpr (STORE_E) {
-                        uint32_t low = 0, big = 0;
-#pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
-                            const R enew = fast_exp2(fmin(dt, R(64)));
-                            const R s_old = Sden[p];
-                            const R s_new = s_old - e[p][k] + enew;
-                            e[p][k] = enew;
-                            Sden[p] = s_new;
-                            low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
-                            big |= (uint32_t)(dt > R(64)) << p;
-                        }
-                        repair_store(low, big);
-                    } else {
-#pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
-                            const R enew = fast_exp2(fmin(dt, R(64)));
-                            const R s_old = Sden[p];
-                            R s_new = s_old - eold[p] + enew;
-                            if (!(s_new > R(1e-4) * s_old)) {
-                                // the particle lost most of its density: re-sum exactly
-                                s_new = enew;
-                                for (int j = 0; j < Kslots; ++j)
-                                    if (j != k && ((alive >> j) & 1u))
-                                        s_new += fast_exp2(fmin(log2_term<R, D>(comp[j], x[p]) - ref[p], R(64)));
-                            }
-                            Sden[p] = (s_new > rebase_below && !(dt > R(64))) ? s_new : rebase_sum(x[p], ref[p]);
-                        }
-                    }
-                }
 
-                // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
-                const R lg2G = fast_log2(G);
-                double lsum[1] = {0.0};
-                R dens[P];
-                uint32_t low = 0;
-                if constexpr (STORE_E) {
+                    // ---- end of sweep: per-particle mixture density, eq. (lnL-GM) ----
+                    const R lg2G = fast_log2(G);
+                    double lsum[1] = {0.0};
+                    R dens[P];
+                    uint32_t low = 0;
+                    if constexpr (STORE_E) {
 #pragma unroll
-                    for (int p = 0; p < P; ++p) dens[p] = resum(e[p]);
-                } else {
-                    // component outer, particles inner: each component's
-                    // parameters are read from LDS once per sweep
+                        for (int p = 0; p < P; ++p) dens[p] = resum(e[p]);
+                    } else {
+                        // component outer, particles inner: each component's
+                        // parameters are read from LDS once per sweep
 #pragma unroll
-                    for (int p = 0; p < P; ++p) dens[p] = R(0);
-                    for (int j = 0; j < Kslots; ++j) {
-                        if (!((alive >> j) & 1u)) continue;
-                        const CompState<R, D> cj = comp[j];
+                        for (int p = 0; p < P; ++p) dens[p] = R(0);
+                        for (int j = 0; j < Kslots; ++j) {
+                            if (!((alive >> j) & 1u)) continue;
+                            const CompState<R, D> cj = comp[j];
 #pragma unroll
-                        for (int p = 0; p < P; ++p)
-                            dens[p] += fast_exp2(fmin(log2_term<R, D>(cj, x[p]) - ref[p], R(64)));
+                            for (int p = 0; p < P; ++p)
+                                dens[p] += fast_exp2(fmin(log2_term<R, D>(cj, x[p]) - ref[p], R(64)));
+                        }
                     }
-                }
 #pragma unroll
-                for (int p = 0; p < P; ++p) low |= (uint32_t)!(dens[p] > rebase_below) << p;
-                if (__builtin_amdgcn_ballot_w64(low != 0) != 0) {
+                    for (int p = 0; p < P; ++p) low |= (uint32_t)!(dens[p] > rebase_below) << p;
+                    if (__builtin_amdgcn_ballot_w64(low != 0) != 0) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            if ((low >> p) & 1u) {
+                                if constexpr (STORE_E)
+                                    dens[p] = rebase_store(e[p], x[p], ref[p]);
+                                else
+                                    dens[p] = rebase_sum(x[p], ref[p]);
+                            }
+                        }
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        if ((low >> p) & 1u) {
-                            if constexpr (STORE_E)
-                                dens[p] = rebase_store(e[p], x[p], ref[p]);
-                            else
-                                dens[p] = rebase_sum(x[p], ref[p]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const R den = dens[p];
-                    const R lg = fast_log2(den);
-                    if constexpr (STORE_E) {
-                        // the weights are normalised below (u_j / G, c_j - log2 G):
-                        // lowering the reference by log2 G keeps every stored term
-                        ref[p] = ref[p] - lg2G;
-                        lsum[0] += (double)a[p] * (double)(ref[p] + lg);  // log2 mixture density at x_p
-                        Sden[p] = den;
-                    } else {
-                        ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
-                        lsum[0] += (double)a[p] * (double)ref[p];
-                        Sden[p] = R(1);
-                    }
-                }
-                block_sum<2, kEmMaxWaves>(lsum, red_d, par_d, nwaves);
-                // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
-                if (lane < Kslots && ((alive >> lane) & 1u)) {
-                    comp[lane].u = comp[lane].u * m_rcp(G);
-                    comp[lane].c2 = comp[lane].c2 - lg2G;
-                }
-                R Gn = R(0);
-                double pen = 0.0;
-                for (int j = 0; j < Kslots; ++j)
-                    if ((alive >> j) & 1u) Gn += comp[j].u;
-                for (int j = 0; j < Kslots; ++j)
-                    if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
-                G = Gn;
-                const double dpar = K * T + K - 1;
-                // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
-                L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
-
-                // ---- compaction of dead slots (rare) ----
-                if (annihilated) {
-                    for (int k = Kslots - 1; k >= 0; --k) {
-                        if ((alive >> k) & 1u) continue;
-                        if (lane == 0)
-                            for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
+                        const R den = dens[p];
+                        const R lg = fast_log2(den);
                         if constexpr (STORE_E) {
-#pragma unroll
-                            for (int j = 0; j + 1 < KMAX; ++j)
-                                if (j >= k) {
-#pragma unroll
-                                    for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
-                                }
-#pragma unroll
-                            for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
+                            // the weights are normalised below (u_j / G, c_j - log2 G):
+                            // lowering the reference by log2 G keeps every stored term
+                            ref[p] = ref[p] - lg2G;
+                            lsum[0] += (double)a[p] * (double)(ref[p] + lg);  // log2 mixture density at x_p
+                            Sden[p] = den;
+                        } else {
+                            ref[p] = ref[p] + lg - lg2G;  // log2 of the normalised mixture density at x_p
+                            lsum[0] += (double)a[p] * (double)ref[p];
+                            Sden[p] = R(1);
                         }
-                        const uint32_t low = alive & ((1u << k) - 1u);
-                        const uint32_t high = (alive >> (k + 1)) << k;
-                        alive = low | high;
-                        --Kslots;
+                    }
+                    block_sum<2, kEmMaxWaves>(lsum, red_d, par_d, nwaves);
+                    // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
+                    if (lane < Kslots && ((alive >> lane) & 1u)) {
+                        comp[lane].u = comp[lane].u * m_rcp(G);
+                        comp[lane].c2 = comp[lane].c2 - lg2G;
+                    }
+                    R Gn = R(0);
+                    double pen = 0.0;
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) Gn += comp[j].u;
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
+                    G = Gn;
+                    const double dpar = K * T + K - 1;
+                    // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
+                    L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
+
+                    // ---- compaction of dead slots (rare) ----
+                    if (annihilated) {
+                        for (int k = Kslots - 1; k >= 0; --k) {
+                            if ((alive >> k) & 1u) continue;
+                            if (lane == 0)
+                                for (int j = k; j + 1 < Kslots; ++j) comp[j] = comp[j + 1];
+                            if constexpr (STORE_E) {
+#pragma unroll
+                                for (int j = 0; j + 1 < KMAX; ++j)
+                                    if (j >= k) {
+#pragma unroll
+                                        for (int p = 0; p < P; ++p) e[p][j] = e[p][j + 1];
+                                    }
+#pragma unroll
+                                for (int p = 0; p < P; ++p) e[p][KMAX - 1] = R(0);
+                            }
+                            const uint32_t low = alive & ((1u << k) - 1u);
+                            const uint32_t high = (alive >> (k + 1)) << k;
+                            alive = low | high;
+                            --Kslots;
+                        }
+                    }
+
+                    if (fixed > 0) {
+                        if (s == fixed) break;
+                        L_prev = L_s;
+                        continue;
+                    }
+                    if (!isfinite(L_s)) break;  // the objective is undefined: no further sweep can help
+                    if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
+                    if (s == max_sweeps) {
+                        status |= GM_ST_MAXSWEEPS;
+                        break;
+                    }
+                    L_prev = L_s;
+                }
+                if (s > cap_sweeps) s = cap_sweeps;
+                s_total += s;
+                if (!outer) break;
+                if (K_best == 0 || L_s > L_best) {
+                    if (wid == 0 && lane < K) bestc[lane] = comp[lane];
+                    L_best = L_s;
+                    K_best = K;
+                    G_best = G;
+                }
+                if (K <= 1 || !isfinite(L_s)) break;
+                // remove the least probable component (smallest weight, lowest
+                // slot on ties); the others keep their parameters and the
+                // weights renormalise through G
+                int kmin = 0;
+                R umin = comp[0].u;
+                for (int j = 1; j < K; ++j) {
+                    const R uj = comp[j].u;
+                    if (uj < umin) {
+                        umin = uj;
+                        kmin = j;
                     }
                 }
-
-                if (fixed > 0) {
-                    if (s == fixed) break;
-                    L_prev = L_s;
-                    continue;
-                }
-                if (!isfinite(L_s)) break;  // the objective is undefined: no further sweep can help
-                if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
-                if (s == max_sweeps) {
-                    status |= GM_ST_MAXSWEEPS;
-                    break;
-                }
-                L_prev = L_s;
+                if (lane == 0)
+                    for (int j = kmin; j + 1 < K; ++j) comp[j] = comp[j + 1];
+                G -= umin;
+                --K;
             }
-            if (s > cap_sweeps) s = cap_sweeps;
+            if (outer && K_best > 0) {
+                __syncthreads();  // the best state, written by wave 0, into every wave's copy
+                if (lane < K_best) comp[lane] = bestc[lane];
+                K = K_best;
+                G = G_best;
+                L_s = L_best;
+            }
+            s = s_total;
             if (!warm || fixed > 0 || L_s >= L_one - 1e-5 * fabs(L_one)) break;
             // rejected warm start: cold start, flags of the cold fit only
             warm = false;
