@@ -79,6 +79,13 @@ def _declare(L):
     L.orc_reconstruct_tensor.restype = ctypes.c_int
     L.orc_project.argtypes = [P, P, P, P, I64, ctypes.c_int, ctypes.c_int, P]
     L.orc_project.restype = ctypes.c_int
+    C = ctypes.c_int
+    L.orc_compress_std.argtypes = [P, P, P, I64, C, C, C, C, C, F64, U64, C, C, P, P, P, P, P, P, P, P, P, P, P, P, C]
+    L.orc_compress_std.restype = C
+    L.orc_aa_solve.argtypes = [C, C, P, P, P]
+    L.orc_aa_solve.restype = C
+    L.orc_kmeans.argtypes = [P, P, C, C, C, P, P, P, P, P]
+    L.orc_kmeans.restype = C
     L.orc_reconstruct.restype = ctypes.c_int
     if hasattr(L, "orc_features"):
         _declare_mlp(L)
@@ -198,6 +205,70 @@ def penalised_L(v, alpha, omega, mu, sigma, T=-1.0):
     n, D = v.shape
     return lib().orc_penalised_L(_p(v), _p(_c(alpha, np.float64)), n, D, len(omega), _p(_c(omega, np.float64)),
                                  _p(_c(mu, np.float64)), _p(_c(sigma, np.float64)), float(T))
+
+
+def compress_std(v, alpha, cell_off, K, seed, kmax=None, kmeans=False, aa_m=0, n_min=10, max_iter=1000, tol=1e-7,
+                 trace=False, nthreads=None):
+    """Standard (non-adaptive) EM of every cell (Sec. 3.4): K components,
+    random or K-means start, Anderson memory aa_m (0: plain EM), then the
+    unpenalised finish.  Returns a dict of arrays; ``ll`` is the
+    log-likelihood at the last iterate, ``resets`` the Anderson resets."""
+    v = _c(v, np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    D = v.shape[1]
+    kmax = K if kmax is None else kmax
+    alpha = _c(alpha, np.float64)
+    off = _c(cell_off, np.int64)
+    n_cells = len(off) - 1
+    nt = ntri(D)
+    out = {
+        "K": np.zeros(n_cells, np.int32), "omega": np.zeros((n_cells, kmax)),
+        "mu": np.zeros((n_cells, kmax, D)), "sigma": np.zeros((n_cells, kmax, nt)),
+        "moments": np.zeros((n_cells, 1 + D + nt)), "ll": np.zeros(n_cells), "L_final": np.zeros(n_cells),
+        "iters": np.zeros(n_cells, np.int32), "status": np.zeros(n_cells, np.int32),
+        "resets": np.zeros(n_cells, np.int32), "kmeans_passes": np.zeros(n_cells, np.int32),
+    }
+    lt = np.full((n_cells, max_iter), np.nan) if trace else None
+    rc = lib().orc_compress_std(_p(v), _p(alpha), _p(off), n_cells, D, kmax, K, n_min, max_iter, tol, seed,
+                                int(kmeans), aa_m, _p(out["K"]), _p(out["omega"]), _p(out["mu"]), _p(out["sigma"]),
+                                _p(out["moments"]), _p(out["ll"]), _p(out["L_final"]), _p(out["iters"]),
+                                _p(out["status"]), _p(out["resets"]), _p(out["kmeans_passes"]), _p(lt),
+                                nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("orc_compress_std rejected its arguments")
+    if trace:
+        out["ll_trace"] = lt
+    return out
+
+
+def kmeans(x, a, K, idx):
+    """K-means (Lloyd) of the standard-EM start on centred particles x with
+    weights a from the particles idx; returns (w, mu, sigma packed, assign,
+    passes) where w sums the assigned weights divided by their total."""
+    x = _c(x, np.float64)
+    n, D = x.shape
+    w = np.zeros(K)
+    mu = np.zeros((K, D))
+    S = np.zeros((K, ntri(D)))
+    asg = np.zeros(n, np.int32)
+    passes = lib().orc_kmeans(_p(x), _p(_c(a, np.float64)), n, D, K, _p(_c(idx, np.int32)), _p(w), _p(mu), _p(S),
+                              _p(asg))
+    if passes < 0:
+        raise ValueError("orc_kmeans rejected its arguments")
+    return w, mu, S, asg, passes
+
+
+def aa_solve(dF, f):
+    """The Anderson least-squares step: gamma = argmin |f - dF gamma| by
+    modified Gram-Schmidt (dF: len x mk).  None when a column is dependent."""
+    dF = np.asarray(dF, dtype=np.float64)
+    cols = _c(dF.T, np.float64)
+    g = np.zeros(dF.shape[1])
+    rc = lib().orc_aa_solve(dF.shape[0], dF.shape[1], _p(cols), _p(_c(f, np.float64)), _p(g))
+    if rc == -2:
+        raise ValueError("orc_aa_solve rejected its arguments")
+    return None if rc != 0 else g
 
 
 def reconstruct(K, omega, mu, sigma, out_off, target, D, dx, seed, stats=False, nthreads=None):

@@ -27,6 +27,7 @@
 
 #define ORC_MAXK 32
 #define ORC_MAXD 3
+#define ORC_AA_MAX 8 /* largest Anderson memory */
 
 /* per-cell status bits (the library documents the same values) */
 #define ORC_SMALL_CELL_K1 (1 << 0)
@@ -1113,4 +1114,542 @@ int orc_reconstruct_tensor(const int32_t* K, const double* w, const double* mu, 
     recon_job J = {K, w, mu, S, kmax, out_off, moments, n_cells, D, dx, seed, v_out, w_out, x_out, status, NULL, 1};
     run_chunks(n_cells, nthreads, recon_worker, &J, sizeof(recon_chunk), fill_recon);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* standard (non-adaptive) EM with K-means initialisation and Anderson */
+/* acceleration (Sec. 3.4)                                             */
+/* ------------------------------------------------------------------ */
+/* The parameter vector accelerated by Anderson mixing holds, per component
+ * in slot order, the weight w_k, the mean mu_k and the second moment
+ * M2_k = Sigma_k + mu_k mu_k^T (packed upper triangle): the paper mixes M2
+ * rather than Sigma because M2 is linear in the mixture. */
+static int std_len(int D) { return 1 + D + ntri(D); }
+
+static void theta_from_mixture(int D, const mixture* m, double* th)
+{
+    const int L = std_len(D);
+    for (int k = 0; k < m->K; ++k) {
+        double* t = th + (size_t)k * L;
+        t[0] = m->w[k];
+        for (int i = 0; i < D; ++i) t[1 + i] = m->mu[k][i];
+        int q = 0;
+        for (int i = 0; i < D; ++i)
+            for (int j = i; j < D; ++j) t[1 + D + q++] = m->S[k][i][j] + m->mu[k][i] * m->mu[k][j];
+    }
+}
+
+/* Decode a parameter vector; returns 0 if every weight is >= 0 and every
+ * Sigma_k = M2_k - mu_k mu_k^T has a Cholesky factor, else -1. */
+static int mixture_from_theta(int D, int K, const double* th, mixture* m)
+{
+    const int L = std_len(D);
+    m->K = K;
+    for (int k = 0; k < K; ++k) {
+        const double* t = th + (size_t)k * L;
+        if (!(t[0] >= 0.0)) return -1;
+        m->w[k] = t[0];
+        for (int i = 0; i < D; ++i) m->mu[k][i] = t[1 + i];
+        int q = 0;
+        for (int i = 0; i < D; ++i)
+            for (int j = i; j < D; ++j) {
+                const double s = t[1 + D + q++] - t[1 + i] * t[1 + j];
+                m->S[k][i][j] = s;
+                m->S[k][j][i] = s;
+            }
+        if (chol(D, (const double(*)[ORC_MAXD])m->S[k], m->L[k]) != 0) return -1;
+    }
+    return 0;
+}
+
+/* One standard EM step G(theta) (joint E-step, eqs. muk, sigmak, omegak-mle).
+ * A component without responsibility (N_k = 0, only possible with w_k = 0)
+ * keeps its mean and covariance and stays at weight 0.  Returns the
+ * log-likelihood sum_p a_p ln sum_k w_k f_k(v_p) at the input parameters. */
+static double std_em_step(int D, const mixture* m, int n, const double* x, const double* a, double N, double* g_all,
+                          mixture* out)
+{
+    const int K = m->K;
+    double gp[ORC_MAXK], ell[ORC_MAXK];
+    double ll = 0.0;
+    for (int p = 0; p < n; ++p) {
+        const double* xp = x + (size_t)p * D;
+        double mx = -INFINITY;
+        for (int j = 0; j < K; ++j) {
+            ell[j] = (m->w[j] > 0.0 ? log(m->w[j]) : -INFINITY) + log_normal(D, xp, m->mu[j], m->L[j]);
+            if (ell[j] > mx) mx = ell[j];
+        }
+        double s = 0.0;
+        for (int j = 0; j < K; ++j) {
+            gp[j] = exp(ell[j] - mx);
+            s += gp[j];
+        }
+        ll += a[p] * (mx + log(s));
+        for (int j = 0; j < K; ++j) g_all[(size_t)j * n + p] = a[p] * gp[j] / s;
+    }
+    *out = *m;
+    for (int k = 0; k < K; ++k) {
+        const double* g = g_all + (size_t)k * n;
+        double Nk = 0.0;
+        for (int p = 0; p < n; ++p) Nk += g[p];
+        if (!(Nk > 0.0)) {
+            out->w[k] = 0.0;
+            continue;
+        }
+        mean_cov(D, n, x, g, Nk, out->mu[k], out->S[k]);
+        out->w[k] = Nk / N;
+    }
+    return ll;
+}
+
+/* K-means (Lloyd) from the given centres on the weighted centred particles,
+ * Euclidean distance, ties to the lowest slot, weighted centroids; a centre
+ * that loses all its particles stays where it is.  Stops when no assignment
+ * changes (or after 100 passes).  On return m holds the initial mixture of
+ * the hard assignment: w_k = W_k / N, mu_k the centroid, Sigma_k the
+ * cluster's weighted covariance (the covariance floor where it does not
+ * factor).  Returns the number of assignment passes. */
+static int kmeans_init(int D, int K, int n, const double* x, const double* a, double N, const int* idx, double trC,
+                       mixture* m, int* assign, int32_t* status)
+{
+    double c[ORC_MAXK][ORC_MAXD];
+    for (int k = 0; k < K; ++k)
+        for (int i = 0; i < D; ++i) c[k][i] = x[(size_t)idx[k] * D + i];
+    for (int p = 0; p < n; ++p) assign[p] = -1;
+    int pass = 0;
+    for (pass = 1; pass <= 100; ++pass) {
+        int changed = 0;
+        for (int p = 0; p < n; ++p) {
+            const double* xp = x + (size_t)p * D;
+            int best = 0;
+            double bd = INFINITY;
+            for (int k = 0; k < K; ++k) {
+                double d2 = 0.0;
+                for (int i = 0; i < D; ++i) d2 += (xp[i] - c[k][i]) * (xp[i] - c[k][i]);
+                if (d2 < bd) {
+                    bd = d2;
+                    best = k;
+                }
+            }
+            if (best != assign[p]) {
+                changed = 1;
+                assign[p] = best;
+            }
+        }
+        if (!changed) break;
+        for (int k = 0; k < K; ++k) {
+            double W = 0.0, s[ORC_MAXD] = {0, 0, 0};
+            for (int p = 0; p < n; ++p)
+                if (assign[p] == k) {
+                    W += a[p];
+                    for (int i = 0; i < D; ++i) s[i] += a[p] * x[(size_t)p * D + i];
+                }
+            if (W > 0.0)
+                for (int i = 0; i < D; ++i) c[k][i] = s[i] / W;
+        }
+    }
+    if (pass > 100) pass = 100;
+    m->K = K;
+    for (int k = 0; k < K; ++k) {
+        double W = 0.0;
+        for (int p = 0; p < n; ++p)
+            if (assign[p] == k) W += a[p];
+        for (int i = 0; i < D; ++i) m->mu[k][i] = c[k][i];
+        m->w[k] = W / N;
+        for (int i = 0; i < D; ++i)
+            for (int j = 0; j < D; ++j) {
+                double s = 0.0;
+                for (int p = 0; p < n; ++p)
+                    if (assign[p] == k) s += a[p] * (x[(size_t)p * D + i] - c[k][i]) * (x[(size_t)p * D + j] - c[k][j]);
+                m->S[k][i][j] = W > 0.0 ? s / W : 0.0;
+            }
+        if (factor_component(D, m, k, trC)) *status |= ORC_COV_FLOOR;
+    }
+    return pass;
+}
+
+/* Least squares min |f - dF gamma| over the columns of dF (len x mk, column
+ * j at dF + j * len) by modified Gram-Schmidt; returns -1 when a column is
+ * numerically dependent on the earlier ones (|R_jj| <= 1e-12 |dF_j|). */
+static int aa_solve(int len, int mk, const double* dF, const double* f, double* gamma)
+{
+    double Q[ORC_AA_MAX][ORC_MAXK * 10], R[ORC_AA_MAX][ORC_AA_MAX], qf[ORC_AA_MAX];
+    for (int j = 0; j < mk; ++j) {
+        double nrm0 = 0.0;
+        for (int t = 0; t < len; ++t) {
+            Q[j][t] = dF[(size_t)j * len + t];
+            nrm0 += Q[j][t] * Q[j][t];
+        }
+        for (int l = 0; l < j; ++l) {
+            double r = 0.0;
+            for (int t = 0; t < len; ++t) r += Q[l][t] * Q[j][t];
+            R[l][j] = r;
+            for (int t = 0; t < len; ++t) Q[j][t] -= r * Q[l][t];
+        }
+        double nrm = 0.0;
+        for (int t = 0; t < len; ++t) nrm += Q[j][t] * Q[j][t];
+        nrm = sqrt(nrm);
+        if (!(nrm > 1e-12 * sqrt(nrm0))) return -1;
+        R[j][j] = nrm;
+        for (int t = 0; t < len; ++t) Q[j][t] /= nrm;
+    }
+    for (int j = 0; j < mk; ++j) {
+        double s = 0.0;
+        for (int t = 0; t < len; ++t) s += Q[j][t] * f[t];
+        qf[j] = s;
+    }
+    for (int j = mk - 1; j >= 0; --j) {
+        double s = qf[j];
+        for (int l = j + 1; l < mk; ++l) s -= R[j][l] * gamma[l];
+        gamma[j] = s / R[j][j];
+    }
+    return 0;
+}
+
+typedef struct {
+    const double* v;
+    const double* alpha;
+    const int64_t* off;
+    int D, kmax, K, n_min, max_iter;
+    double tol;
+    uint64_t seed;
+    int kmeans, aa_m;
+    int32_t* Kout;
+    double* w;
+    double* mu;
+    double* S;
+    double* mom;
+    double* ll_out;
+    double* L_final;
+    int32_t* iters;
+    int32_t* status;
+    int32_t* resets;
+    int32_t* kmeans_passes;
+    double* ll_trace; /* nullable [n_cells * max_iter] */
+} std_job;
+
+/* Standard (non-adaptive) EM of one cell, Sec. 3.4: K0 = min(K, n)
+ * components started at the cold-start particles (or K-means from them),
+ * then G(theta) iterations, Anderson-mixed when aa_m > 0 (Walker & Ni, the
+ * unconstrained difference form: theta_{i+1} = G(theta_i) - dG gamma with
+ * gamma = argmin |f_i - dF gamma|, f = G(theta) - theta, dF/dG the last
+ * min(aa_m, i) differences).  A mixed state with a negative weight or an
+ * indefinite Sigma, or a dependent least-squares column, resets the
+ * mixing: the step becomes G(theta_i) and the history restarts from it.
+ * Mixed weights are renormalised to sum 1.  Stop when the log-likelihood
+ * at theta_i changes by at most tol relative, or after max_iter
+ * iterations; the state theta_i is the result, and the unpenalised joint
+ * step of the finish (Sec. 2.3.1) is the standard EM step that follows it. */
+static void std_cell(const std_job* J, int64_t c, double* x, double* a, double* g, int* assign, double* hist)
+{
+    const int D = J->D, nt = ntri(D), L = std_len(D);
+    const int64_t o0 = J->off[c], o1 = J->off[c + 1];
+    const int n = (int)(o1 - o0);
+    const double T = 0.5 * D * (D + 3);
+    const double* v = J->v + (size_t)o0 * D;
+    const double* al = J->alpha + o0;
+    int32_t status = 0;
+    mixture m;
+    memset(&m, 0, sizeof(m));
+    double* mom = J->mom + (size_t)c * (1 + D + nt);
+    for (int i = 0; i < 1 + D + nt; ++i) mom[i] = 0.0;
+    J->ll_out[c] = 0.0;
+    J->L_final[c] = 0.0;
+    J->iters[c] = 0;
+    J->resets[c] = 0;
+    J->kmeans_passes[c] = 0;
+    compress_job W0;
+    memset(&W0, 0, sizeof(W0));
+    W0.D = D;
+    W0.kmax = J->kmax;
+    W0.K = J->Kout;
+    W0.w = J->w;
+    W0.mu = J->mu;
+    W0.S = J->S;
+    double zero[ORC_MAXD] = {0, 0, 0};
+    for (int p = 0; p < n; ++p) {
+        int bad = !isfinite(al[p]) || !(al[p] > 0.0);
+        for (int i = 0; i < D; ++i) bad |= !isfinite(v[(size_t)p * D + i]);
+        if (bad) {
+            m.K = 0;
+            write_mixture(&W0, c, &m, zero);
+            J->status[c] = ORC_NONFINITE_INPUT;
+            return;
+        }
+    }
+    if (n == 0) {
+        m.K = 0;
+        write_mixture(&W0, c, &m, zero);
+        J->status[c] = ORC_DEGENERATE;
+        return;
+    }
+    /* moments, centring and weights summing to N = n, as for compress */
+    double W = 0.0, P[ORC_MAXD] = {0, 0, 0}, S2[ORC_MAXD][ORC_MAXD];
+    memset(S2, 0, sizeof(S2));
+    for (int p = 0; p < n; ++p) {
+        W += al[p];
+        for (int i = 0; i < D; ++i) {
+            P[i] += al[p] * v[(size_t)p * D + i];
+            for (int j = 0; j < D; ++j) S2[i][j] += al[p] * v[(size_t)p * D + i] * v[(size_t)p * D + j];
+        }
+    }
+    mom[0] = W;
+    for (int i = 0; i < D; ++i) mom[1 + i] = P[i];
+    pack_sym(D, (const double(*)[ORC_MAXD])S2, mom + 1 + D);
+    double mean[ORC_MAXD] = {0, 0, 0};
+    for (int i = 0; i < D; ++i) mean[i] = P[i] / W;
+    double C[ORC_MAXD][ORC_MAXD];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double s = 0.0;
+            for (int p = 0; p < n; ++p) s += al[p] * (v[(size_t)p * D + i] - mean[i]) * (v[(size_t)p * D + j] - mean[j]);
+            C[i][j] = s / W;
+        }
+    double trC = 0.0;
+    for (int i = 0; i < D; ++i) trC += C[i][i];
+    const double N = (double)n;
+    for (int p = 0; p < n; ++p) {
+        a[p] = al[p] * (double)n / W;
+        for (int i = 0; i < D; ++i) x[(size_t)p * D + i] = v[(size_t)p * D + i] - mean[i];
+    }
+    double LC[ORC_MAXD][ORC_MAXD];
+    const int c_spd = chol(D, (const double(*)[ORC_MAXD])C, LC) == 0;
+    if (n <= J->n_min || !c_spd) {
+        m.K = 1;
+        m.w[0] = 1.0;
+        memcpy(m.S[0], C, sizeof(C));
+        memcpy(m.L[0], LC, sizeof(LC));
+        status |= c_spd ? ORC_SMALL_CELL_K1 : (ORC_SMALL_CELL_K1 | ORC_DEGENERATE);
+        J->L_final[c] = c_spd ? penalised_L(D, T, &m, n, x, a, N) : -INFINITY;
+        J->ll_out[c] = J->L_final[c];
+        write_mixture(&W0, c, &m, mean);
+        J->status[c] = status;
+        return;
+    }
+    /* start: the cold-start particles, K0 = min(K, n) (no penalty, no cap) */
+    const int K0 = J->K < n ? J->K : n;
+    int* perm = (int*)malloc(sizeof(int) * (size_t)n);
+    orc_init_indices(n, K0, J->seed, (uint64_t)c, perm);
+    if (J->kmeans) {
+        J->kmeans_passes[c] = kmeans_init(D, K0, n, x, a, N, perm, trC, &m, assign, &status);
+    } else {
+        m.K = K0;
+        for (int k = 0; k < K0; ++k) {
+            m.w[k] = 1.0 / K0;
+            for (int i = 0; i < D; ++i) m.mu[k][i] = x[(size_t)perm[k] * D + i];
+            memcpy(m.S[k], C, sizeof(C));
+            memcpy(m.L[k], LC, sizeof(LC));
+        }
+    }
+    free(perm);
+    /* iterations: hist holds up to aa_m + 1 pairs (f, G) of length len */
+    const int len = K0 * L, mmax = J->aa_m;
+    double* th = hist;                        /* theta_i */
+    double* fg = th + (size_t)len;            /* G(theta_i) */
+    double* Fh = fg + (size_t)len;            /* ring of f, (mmax + 1) x len */
+    double* Gh = Fh + (size_t)(mmax + 1) * len; /* ring of G, (mmax + 1) x len */
+    double* dF = Gh + (size_t)(mmax + 1) * len; /* mmax x len */
+    double* dG = dF + (size_t)mmax * len;
+    double gamma[ORC_AA_MAX];
+    theta_from_mixture(D, &m, th);
+    int nh = 0, head = 0, resets = 0, it = 0, mixed = 0, have_prev = 0, converged = 0;
+    double ll = 0.0, ll_prev = 0.0;
+    mixture gm, g_acc;
+    memset(&g_acc, 0, sizeof(g_acc));
+    while (it < J->max_iter) {
+        ++it;
+        ll = std_em_step(D, &m, n, x, a, N, g, &gm);
+        if (J->ll_trace) J->ll_trace[(size_t)c * J->max_iter + (it - 1)] = ll;
+        if (mixed && !(ll >= ll_prev)) {
+            /* the mixed iterate lowered the likelihood: back to the plain
+             * step of the last accepted iterate, history cleared */
+            ++resets;
+            m = g_acc;
+            m.K = K0;
+            for (int k = 0; k < K0; ++k)
+                if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+            theta_from_mixture(D, &m, th);
+            nh = 0;
+            head = 0;
+            mixed = 0;
+            continue;
+        }
+        if (have_prev && fabs(ll - ll_prev) <= J->tol * fabs(ll)) {
+            converged = 1;
+            break;
+        }
+        if (!isfinite(ll)) break;
+        ll_prev = ll;
+        have_prev = 1;
+        g_acc = gm;
+        theta_from_mixture(D, &gm, fg);
+        int take_g = 1;
+        mixed = 0;
+        if (mmax > 0) {
+            /* push (f_i, G_i) */
+            double* fslot = Fh + (size_t)head * len;
+            double* gslot = Gh + (size_t)head * len;
+            for (int t = 0; t < len; ++t) {
+                fslot[t] = fg[t] - th[t];
+                gslot[t] = fg[t];
+            }
+            head = (head + 1) % (mmax + 1);
+            if (nh < mmax + 1) ++nh;
+            const int mk = nh - 1;
+            if (mk >= 1) {
+                /* columns j = 0..mk-1: oldest difference first */
+                for (int j = 0; j < mk; ++j) {
+                    const int i0 = (head - nh + j + 2 * (mmax + 1)) % (mmax + 1);
+                    const int i1 = (i0 + 1) % (mmax + 1);
+                    for (int t = 0; t < len; ++t) {
+                        dF[(size_t)j * len + t] = Fh[(size_t)i1 * len + t] - Fh[(size_t)i0 * len + t];
+                        dG[(size_t)j * len + t] = Gh[(size_t)i1 * len + t] - Gh[(size_t)i0 * len + t];
+                    }
+                }
+                const double* fcur = Fh + (size_t)((head + mmax) % (mmax + 1)) * len;
+                if (aa_solve(len, mk, dF, fcur, gamma) == 0) {
+                    double cand[ORC_MAXK * 10];
+                    for (int t = 0; t < len; ++t) {
+                        double s = fg[t];
+                        for (int j = 0; j < mk; ++j) s -= gamma[j] * dG[(size_t)j * len + t];
+                        cand[t] = s;
+                    }
+                    double ws = 0.0;
+                    for (int k = 0; k < K0; ++k) ws += cand[(size_t)k * L];
+                    for (int k = 0; k < K0; ++k) cand[(size_t)k * L] /= ws;
+                    mixture cm;
+                    if (ws > 0.0 && mixture_from_theta(D, K0, cand, &cm) == 0) {
+                        memcpy(th, cand, sizeof(double) * (size_t)len);
+                        m = cm;
+                        take_g = 0;
+                        mixed = 1;
+                    }
+                }
+                if (take_g) {
+                    /* no usable mixed iterate: the plain step, and the
+                     * history restarts from the latest pair */
+                    ++resets;
+                    const int last = (head + mmax) % (mmax + 1);
+                    if (last != 0) {
+                        memcpy(Fh, Fh + (size_t)last * len, sizeof(double) * (size_t)len);
+                        memcpy(Gh, Gh + (size_t)last * len, sizeof(double) * (size_t)len);
+                    }
+                    nh = 1;
+                    head = 1 % (mmax + 1);
+                }
+            }
+        }
+        if (take_g) {
+            /* G keeps Sigma positive definite unless a component collapsed */
+            m = gm;
+            m.K = K0;
+            for (int k = 0; k < K0; ++k)
+                if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
+            theta_from_mixture(D, &m, th);
+        }
+    }
+    if (!converged) status |= ORC_MAXSWEEPS;
+    J->iters[c] = it;
+    J->resets[c] = resets;
+    J->ll_out[c] = ll;
+    /* components left without weight are dropped */
+    for (int k = m.K - 1; k >= 0; --k)
+        if (!(m.w[k] > 0.0)) remove_component(&m, k);
+    renormalise(&m);
+    if (mle_finish(D, &m, n, x, a, N, g) != 0) {
+        m.K = 1;
+        m.w[0] = 1.0;
+        memcpy(m.S[0], C, sizeof(C));
+        memcpy(m.L[0], LC, sizeof(LC));
+        memset(m.mu[0], 0, sizeof(m.mu[0]));
+        status |= ORC_DEGENERATE;
+    }
+    J->L_final[c] = penalised_L(D, T, &m, n, x, a, N);
+    write_mixture(&W0, c, &m, mean);
+    J->status[c] = status;
+}
+
+typedef struct {
+    const std_job* J;
+    int64_t c0, c1;
+} std_chunk;
+
+static void* std_worker(void* arg)
+{
+    std_chunk* ch = (std_chunk*)arg;
+    const std_job* J = ch->J;
+    int64_t nmax = max_cell_len(J->off, ch->c0, ch->c1);
+    if (nmax < 1) nmax = 1;
+    const size_t len = (size_t)J->K * std_len(J->D);
+    double* x = (double*)malloc(sizeof(double) * (size_t)nmax * J->D);
+    double* a = (double*)malloc(sizeof(double) * (size_t)nmax);
+    double* g = (double*)malloc(sizeof(double) * (size_t)nmax * ORC_MAXK);
+    int* assign = (int*)malloc(sizeof(int) * (size_t)nmax);
+    double* hist = (double*)malloc(sizeof(double) * len * (2 + 4 * (size_t)J->aa_m + 2));
+    for (int64_t c = ch->c0; c < ch->c1; ++c) std_cell(J, c, x, a, g, assign, hist);
+    free(x);
+    free(a);
+    free(g);
+    free(assign);
+    free(hist);
+    return NULL;
+}
+
+static void fill_std(void* chunk, void* job, int64_t c0, int64_t c1)
+{
+    std_chunk* ch = (std_chunk*)chunk;
+    ch->J = (const std_job*)job;
+    ch->c0 = c0;
+    ch->c1 = c1;
+}
+
+/* Standard EM of every cell (Sec. 3.4): K components (K <= kmax), random
+ * or K-means start, Anderson memory aa_m (0 = plain EM, at most 8). */
+int orc_compress_std(const double* v, const double* alpha, const int64_t* off, int64_t n_cells, int D, int kmax,
+                     int K, int n_min, int max_iter, double tol, uint64_t seed, int kmeans, int aa_m, int32_t* Kout,
+                     double* w, double* mu, double* S, double* mom, double* ll_out, double* L_final, int32_t* iters,
+                     int32_t* status, int32_t* resets, int32_t* kmeans_passes, double* ll_trace, int nthreads)
+{
+    if (D < 1 || D > ORC_MAXD || kmax < 1 || kmax > ORC_MAXK || K < 1 || K > kmax || max_iter < 1 || aa_m < 0 ||
+        aa_m > ORC_AA_MAX)
+        return -1;
+    std_job J = {v, alpha, off, D, kmax, K, n_min, max_iter, tol, seed, kmeans, aa_m, Kout, w, mu, S, mom, ll_out,
+                 L_final, iters, status, resets, kmeans_passes, ll_trace};
+    run_chunks(n_cells, nthreads, std_worker, &J, sizeof(std_chunk), fill_std);
+    return 0;
+}
+
+/* Test entry: the Anderson least-squares step on given columns. */
+int orc_aa_solve(int len, int mk, const double* dF, const double* f, double* gamma)
+{
+    if (len < 1 || len > ORC_MAXK * 10 || mk < 1 || mk > ORC_AA_MAX) return -2;
+    return aa_solve(len, mk, dF, f, gamma);
+}
+
+/* Test entry: K-means from the given start indices on centred particles x
+ * (n x D) with weights a; writes the hard-assignment mixture (w, mu, S
+ * packed) and the assignment; returns the number of passes. */
+int orc_kmeans(const double* x, const double* a, int n, int D, int K, const int* idx, double* w, double* mu,
+               double* S, int* assign)
+{
+    if (D < 1 || D > ORC_MAXD || K < 1 || K > ORC_MAXK || n < 1) return -1;
+    double N = 0.0, trC = 0.0;
+    for (int p = 0; p < n; ++p) N += a[p];
+    for (int i = 0; i < D; ++i) {
+        double m = 0.0, s = 0.0;
+        for (int p = 0; p < n; ++p) m += a[p] * x[(size_t)p * D + i];
+        m /= N;
+        for (int p = 0; p < n; ++p) s += a[p] * (x[(size_t)p * D + i] - m) * (x[(size_t)p * D + i] - m);
+        trC += s / N;
+    }
+    mixture m;
+    memset(&m, 0, sizeof(m));
+    int32_t st = 0;
+    const int passes = kmeans_init(D, K, n, x, a, N, idx, trC, &m, assign, &st);
+    for (int k = 0; k < K; ++k) {
+        w[k] = m.w[k];
+        for (int i = 0; i < D; ++i) mu[(size_t)k * D + i] = m.mu[k][i];
+        pack_sym(D, (const double(*)[ORC_MAXD])m.S[k], S + (size_t)k * ntri(D));
+    }
+    return passes;
 }
