@@ -93,6 +93,7 @@ def parse():
     p.add_argument("--epochs", type=int, default=50)
     p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
     p.add_argument("--no-outer", action="store_true", help="skip the outer-search-over-K measurement")
+    p.add_argument("--no-standard", action="store_true", help="skip the standard-EM (K-means, Anderson) measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     p.add_argument("--no-tune", action="store_true", help="keep the built-in EM launch plans (no gm_autotune)")
@@ -214,6 +215,30 @@ def phase_times(fn, reps, api, torch):
             ph["warm_init"].append(t)
     api.profile_enable(False)
     return {k: float(np.mean(x)) for k, x in ph.items() if x}
+
+
+def standard_em_report(v, alpha, off, D, kmax, W, reps, api, torch):
+    """The standard (fixed-K) EM of Sec. 3.4 on the same batch with K = kmax / 2:
+    random or K-means start, plain or Anderson-mixed (memory 5): time per
+    compress, iterations, log-likelihood at the last iterate."""
+    import numpy as np
+    n_cells = off.numel() - 1
+    n_tot = alpha.numel()
+    K = max(1, kmax // 2)
+    out = {"K": K}
+    for name, km, m in (("random_plain", False, 0), ("kmeans_plain", True, 0), ("random_anderson5", False, 5),
+                        ("kmeans_anderson5", True, 5)):
+        s = api.StandardEM(n_cells, n_tot, D, kmax, device=off.device, seed=W["init_seed"])
+        ms = time_steps(lambda: s(v, alpha, off, K, kmeans=km, aa_memory=m), reps, 1, torch)
+        o = {k: t.cpu().numpy() for k, t in s.out.as_dict().items()}
+        it = o["sweeps"]
+        out[name] = {"ms_per_compress": ms, "mean_iterations": float(it.mean()),
+                     "p50_iterations": float(np.median(it)), "p99_iterations": float(np.quantile(it, 0.99)),
+                     "capped_cells": int(((o["status"] & 8) != 0).sum()),
+                     "mean_loglik": float(np.mean(o["L_pen"][np.isfinite(o["L_pen"])])),
+                     "anderson_resets_per_cell": float(s.resets.float().mean().item())}
+        del s
+    return out
 
 
 def outer_k_search(v, alpha, off, D, kmax, W, cold, reps, api, torch):
@@ -484,6 +509,8 @@ def main():
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
     }
     line.update(line_extra)
+    if not args.no_standard:
+        line["standard_em"] = standard_em_report(v, alpha, off, D, kmax, W, max(1, min(args.steps, 3)), api, torch)
     if not args.no_outer:
         line["outer_k_search"] = outer_k_search(v, alpha, off, D, kmax, W, cold, max(1, min(args.steps, 3)), api,
                                                 torch)

@@ -187,6 +187,46 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
 /* Forget every tuned plan; gm_compress returns to the built-in plans. */
 int gm_autotune_reset(void);
 
+/* ---- standard EM with K-means start and Anderson acceleration ----
+ * The non-adaptive EM of Sec. 3.4 (fixed K, joint E-step, weights N_k / N),
+ * as the paper uses to study faster convergence.  Per cell, K0 = min(K, n)
+ * components start at the cold-start particles of gm_compress (the same
+ * Philox draw, without the floor(N/T) cap) with the cell covariance and
+ * equal weights, or (kmeans = 1) at the mixture of a K-means clustering
+ * started from those particles (Lloyd's algorithm in FP64 on the centred
+ * velocities, Euclidean distance, ties to the lowest slot, weighted
+ * centroids, an emptied centre stays put, at most 100 passes; weights W_k /
+ * N, centroids, cluster covariances).  Iterations apply the EM map G (FP32
+ * E-step and sums) to theta = (w_k, mu_k, M2_k = Sigma_k + mu_k mu_k^T) and,
+ * with aa_memory = m > 0, mix it by Anderson acceleration in FP64
+ * (theta_{i+1} = G(theta_i) - dG gamma, gamma the least-squares
+ * coefficients of f_i = G(theta_i) - theta_i on the last min(m, i)
+ * differences of f, by modified Gram-Schmidt).  A mixed iterate with a
+ * negative weight or an indefinite Sigma, or a numerically dependent
+ * difference, resets the history and takes G(theta_i); a mixed iterate
+ * whose log-likelihood is below the last accepted one's is replaced by G of
+ * that iterate.  Stop when the log-likelihood changes by at most tol_rel
+ * (relative) between accepted iterates or after max_sweeps evaluations of
+ * G; the unpenalised joint FP64 step of gm_compress then follows (it is the
+ * standard EM step after the iteration and restores the moments exactly).
+ *
+ * Output record as gm_compress, with: K the components left with weight;
+ * L_pen the log-likelihood sum_p a_p ln sum_k w_k f_k(v_p) at the last
+ * iterate (a normalised to sum n); L_final the penalised likelihood of the
+ * output; sweeps the evaluations of G; visits sweeps * K0; MAXSWEEPS when
+ * the cap was reached.  resets [n_cells] (Anderson resets and rejections),
+ * kmeans_passes [n_cells] and ll_trace [n_cells * max_sweeps] (the
+ * log-likelihood at every evaluation; untouched after the last) are
+ * nullable device arrays.  n_tot = cell_off[n_cells] (a cell reaching
+ * beyond n_tot is not fitted: K = 0, GM_ST_DEGENERATE).  Options: as
+ * gm_compress, estep_fp64 = 0 (else GM_ENOTIMPL), outer_k = 0; 1 <= K <=
+ * kmax; 0 <= aa_memory <= 5. */
+size_t gm_compress_standard_workspace(int64_t n_cells, int64_t n_tot, const gm_opts* o);
+int gm_compress_standard(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                         int64_t n_tot, const gm_opts* o, int32_t K, int32_t kmeans, int32_t aa_memory,
+                         const gm_mix* out, int32_t* resets, int32_t* kmeans_passes, double* ll_trace, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /* Bytes of workspace gm_reconstruct needs (currently 0; pass NULL). */
 size_t gm_reconstruct_workspace(int64_t n_cells, int32_t D);
 

@@ -42,7 +42,7 @@ class GmInit(ctypes.Structure):
 
 EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
-           "gm_gauss_correct",
+           "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
            "gm_warm_set_params", "gm_warm_gradients", "gm_warm_features", "gm_warm_forward_workspace",
            "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_profile_enable",
@@ -93,6 +93,11 @@ def load():
     L.gm_gauss_correct.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double,
                                    ctypes.c_int32, P, ctypes.c_size_t, P, P, P]
     L.gm_gauss_correct.restype = ctypes.c_int
+    L.gm_compress_standard_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, P]
+    L.gm_compress_standard_workspace.restype = ctypes.c_size_t
+    L.gm_compress_standard.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, P, P, P, P, P, ctypes.c_size_t, P]
+    L.gm_compress_standard.restype = ctypes.c_int
     I32, I64, SZ, U64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_float
     L.gm_warm_param_count.argtypes = []
     L.gm_warm_param_count.restype = SZ

@@ -143,6 +143,40 @@ class Compressor:
                 "variant": [int(x) for x in r[2 + nb:2 + 2 * nb]], "lane": [int(x) for x in r[2 + 2 * nb:2 + 3 * nb]]}
 
 
+class StandardEM:
+    """Reusable standard-EM call (gm_compress_standard) for a fixed batch
+    shape: owns the output record, the diagnostics and the workspace."""
+
+    def __init__(self, n_cells, n_tot, D, kmax, device="cuda", trace=False, **opt):
+        self.opts = make_opts(D, kmax, **opt)
+        self.out = MixtureBuffers(n_cells, D, kmax, device)
+        self.n_cells, self.n_tot = n_cells, n_tot
+        L = _lib.load()
+        nbytes = L.gm_compress_standard_workspace(n_cells, n_tot, ctypes.byref(self.opts))
+        if nbytes == 0:
+            raise ValueError("invalid options")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.resets = torch.zeros(n_cells, dtype=torch.int32, device=device)
+        self.kmeans_passes = torch.zeros(n_cells, dtype=torch.int32, device=device)
+        self.ll_trace = (torch.full((n_cells, self.opts.max_sweeps), float("nan"), dtype=torch.float64,
+                                    device=device) if trace else None)
+        self._mix = self.out.struct()
+
+    def __call__(self, v, alpha, cell_off, K, kmeans=False, aa_memory=0, stream=None):
+        _need(v, torch.float64, "v")
+        _need(alpha, torch.float64, "alpha")
+        _need(cell_off, torch.int64, "cell_off")
+        if cell_off.numel() != self.n_cells + 1 or alpha.numel() != self.n_tot:
+            raise ValueError("batch does not match the shape this call was made for")
+        rc = _lib.load().gm_compress_standard(_ptr(v), _ptr(alpha), _ptr(cell_off), self.n_cells, self.n_tot,
+                                              ctypes.byref(self.opts), int(K), 1 if kmeans else 0, int(aa_memory),
+                                              ctypes.byref(self._mix), _ptr(self.resets),
+                                              _ptr(self.kmeans_passes), _ptr(self.ll_trace), _ptr(self.ws),
+                                              self.ws.numel(), _stream(stream))
+        check(rc, "gm_compress_standard")
+        return self.out
+
+
 def compress(v, alpha, cell_off, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed=0, fp64=False, fixed_sweeps=None,
              init=None, stream=None, outer_k=False):
     """Adaptive EM-GM compress of every cell.  Returns a dict of GPU tensors

@@ -21,6 +21,8 @@ int launch_compress_requeue_d1(const CompressArgs&, hipStream_t);
 int launch_compress_requeue_d3(const CompressArgs&, hipStream_t);
 int launch_compress_finish_d1(int, const CompressArgs&, hipStream_t);
 int launch_compress_finish_d3(int, const CompressArgs&, hipStream_t);
+int launch_std_d1(const StdArgs&, int64_t, hipStream_t);
+int launch_std_d3(const StdArgs&, int64_t, hipStream_t);
 }  // namespace gm
 
 namespace {
@@ -272,6 +274,68 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
     rc = D == 1 ? gm::launch_compress_finish_d1(kt, a, st) : gm::launch_compress_finish_d3(kt, a, st);
     prof_mark(EV_END, st);
     return rc ? GM_EHIP : GM_OK;
+}
+
+size_t gm_compress_standard_workspace(int64_t n_cells, int64_t n_tot, const gm_opts* o)
+{
+    if (!valid_opts(o) || n_cells < 0 || n_tot < 0) return 0;
+    return ws_layout(n_cells, o->D).total + align256((size_t)n_tot * (o->D + 1) * sizeof(float)) +
+           align256((size_t)n_tot * sizeof(int32_t));
+}
+
+int gm_compress_standard(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                         int64_t n_tot, const gm_opts* o, int32_t K, int32_t kmeans, int32_t aa_memory,
+                         const gm_mix* out, int32_t* resets, int32_t* kmeans_passes, double* ll_trace, void* ws,
+                         size_t ws_bytes, void* stream)
+{
+    if (!valid_opts(o) || o->outer_k != 0 || n_cells < 0 || n_cells > 0x7fffffff || n_tot < 0 || !out)
+        return GM_EINVAL;
+    if (K < 1 || K > o->kmax || (kmeans != 0 && kmeans != 1) || aa_memory < 0 || aa_memory > gm::kStdAaMax)
+        return GM_EINVAL;
+    if (o->estep_fp64 != 0) return GM_ENOTIMPL;
+    if (n_cells == 0) return GM_OK;
+    if (!v || !alpha || !cell_off) return GM_EINVAL;
+    if (!out->K || !out->omega || !out->mu || !out->sigma || !out->moments || !out->L_pen || !out->L_final ||
+        !out->sweeps || !out->status || !out->visits)
+        return GM_EINVAL;
+    const WsLayout L = ws_layout(n_cells, o->D);
+    const size_t need = gm_compress_standard_workspace(n_cells, n_tot, o);
+    if (!ws || ws_bytes < need) return GM_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    gm::StdArgs p;
+    memset(&p, 0, sizeof(p));
+    gm::CompressArgs& a = p.a;
+    a.v = v;
+    a.alpha = alpha;
+    a.off = cell_off;
+    a.n_cells = n_cells;
+    a.cells = w + L.cells;
+    a.list = (int32_t*)(w + L.list);
+    a.init_idx = (int32_t*)(w + L.init);
+    a.plan = (int32_t*)(w + L.plan);
+    a.kmax = o->kmax;
+    a.n_min = o->n_min;
+    a.max_sweeps = o->max_sweeps;
+    a.tol = o->tol_rel;
+    a.seed = o->seed;
+    a.std_K = K;
+    a.out = *out;
+    p.n_tot = n_tot;
+    p.xa_w = (float*)(w + L.total);
+    p.assign = (int32_t*)(w + L.total + align256((size_t)n_tot * (o->D + 1) * sizeof(float)));
+    p.K = K;
+    p.kmeans = kmeans;
+    p.aa_m = aa_memory;
+    p.resets = resets;
+    p.kmeans_passes = kmeans_passes;
+    p.ll_trace = ll_trace;
+    const int kt = o->kmax <= 8 ? 8 : 16;
+    const int D = o->D;
+    if (D == 1 ? gm::launch_compress_pre_d1(a, st) : gm::launch_compress_pre_d3(a, st)) return GM_EHIP;
+    if (D == 1 ? gm::launch_std_d1(p, n_cells, st) : gm::launch_std_d3(p, n_cells, st)) return GM_EHIP;
+    if (D == 1 ? gm::launch_compress_finish_d1(kt, a, st) : gm::launch_compress_finish_d3(kt, a, st)) return GM_EHIP;
+    return GM_OK;
 }
 
 int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,

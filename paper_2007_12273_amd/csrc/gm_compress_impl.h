@@ -71,6 +71,7 @@ struct CompressArgs {
     int32_t nwaves;
     int32_t kmax, n_min, max_sweeps;
     int32_t outer;           // 1: outer search over K (gm_opts.outer_k)
+    int32_t std_K;           // > 0: standard EM with this K (start of min(K, n) particles, no cap)
     double tol;
     uint64_t seed;
     const int32_t* fixed;    // nullable
@@ -79,6 +80,21 @@ struct CompressArgs {
 };
 
 enum { PLAN_COUNT = 0, PLAN_BASE = 16, PLAN_CURSOR = 32, PLAN_QUEUE = 48, PLAN_SIZE = 64 };
+
+// standard EM (gm_std.hip)
+constexpr int kStdAaMax = 5;  // largest Anderson memory
+struct StdArgs {
+    CompressArgs a;
+    int64_t n_tot;        // particles the staging buffers hold
+    float* xa_w;          // [n_tot * (D + 1)] centred FP32 velocities and weights a_p (sum N)
+    int32_t* assign;      // [n_tot] K-means labels
+    int32_t K;            // components requested (<= kmax)
+    int32_t kmeans;       // 1: K-means start
+    int32_t aa_m;         // Anderson memory, 0 = plain EM
+    int32_t* resets;      // nullable [n_cells]
+    int32_t* kmeans_passes;  // nullable [n_cells]
+    double* ll_trace;     // nullable [n_cells * max_sweeps]
+};
 constexpr int kInitSlots = 16;
 
 constexpr double kSqrtHalfLog2e = 0.84932180028801904272;  // sqrt(log2(e) / 2)
@@ -188,9 +204,9 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
             // (seed, "INIT") and counter (j, cell, 0, 0).  The permutation is
             // kept as a sparse record of the swapped positions.
             const double T = 0.5 * D * (D + 3);
-            int K = min(A.kmax, n);
+            int K = min(A.std_K > 0 ? A.std_K : A.kmax, n);
             const int cap = max(1, (int)floor((double)n / T));
-            if (K > cap) K = cap;
+            if (A.std_K == 0 && K > cap) K = cap;
             int pos[2 * kInitSlots], val[2 * kInitSlots], nrec = 0;
             for (int j = 0; j < K; ++j) {
                 const u64x4 r = philox4x64_10((uint64_t)j, (uint64_t)c, 0, 0, A.seed, kTagInit);

@@ -77,3 +77,15 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 0.0, 50, p, 1 << 20, None, None, None) == -1  # tol
     assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 1e-12, 0, p, 1 << 20, None, None, None) == -1  # max_iter
     assert lib.gm_gauss_correct(p, p, p, 10, 1, 10, p, 1e-12, 50, p, 16, None, None, None) == -3  # small workspace
+    # standard EM: K, memory, precision and option checks before any launch
+    lib.gm_opts_default(ctypes.byref(o), 3, 8)
+    assert lib.gm_compress_standard_workspace(100, 5000, ctypes.byref(o)) > 5000 * 16
+    mix = _lib.GmMix()
+    args = lambda K, km, m: (None, None, None, 4, 100, ctypes.byref(o), K, km, m, ctypes.byref(mix), None, None, None,
+                             None, 0, None)
+    assert lib.gm_compress_standard(*args(0, 0, 0)) == -1    # K < 1
+    assert lib.gm_compress_standard(*args(9, 0, 0)) == -1    # K > kmax
+    assert lib.gm_compress_standard(*args(4, 2, 0)) == -1    # kmeans not 0/1
+    assert lib.gm_compress_standard(*args(4, 0, 6)) == -1    # memory above 5
+    o.estep_fp64 = 1
+    assert lib.gm_compress_standard(*args(4, 0, 3)) == -4    # FP64 iterations not built
