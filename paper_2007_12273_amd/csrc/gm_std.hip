@@ -72,16 +72,21 @@ __device__ __forceinline__ bool spd64(const double (&S)[ntri(D)])
     return chol<D, double>(S, L);
 }
 
+constexpr int kStdThreads = 256;
+constexpr int kStdWaves = kStdThreads / 64;
+
 template <int D, int KMAX>
-__global__ __launch_bounds__(64) void k_std(StdArgs P)
+__global__ __launch_bounds__(kStdThreads) void k_std(StdArgs P)
 {
     constexpr int NT = ntri(D);
     constexpr int NS = 1 + D + NT;      // M-step sums per component
     constexpr int L = std_len<D>();     // mixed parameters per component
     constexpr int LEN = KMAX * L;
     constexpr int R = kStdAaMax + 1;    // history ring
+    constexpr int NKM = KMAX * (1 + D); // K-means sums
     const CompressArgs& A = P.a;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
     const int c = blockIdx.x;
     const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
     if (ci->kind != CELL_EM) return;
@@ -90,7 +95,12 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
     __shared__ double th[LEN];                  // theta_i, component k at k * L
     __shared__ double Fh[R][LEN], Gh[R][LEN];   // ring of (f, G); G of the last accepted iterate is the newest
     __shared__ double Q[kStdAaMax][LEN];        // orthonormalised differences of f
+    __shared__ float red_f[kStdWaves][KMAX * NS];
     __shared__ float tot[KMAX * NS];
+    __shared__ double red_d[2 * kMaxWaves * NKM];
+    __shared__ double ctr[KMAX][D];
+    __shared__ int s_ctl, s_status, s_resets;
+    int par = 0;
 
     const int n = ci->n;
     const int64_t o0 = A.off[c];
@@ -101,22 +111,25 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
     const double lnc0 = -0.5 * D * kLnTwoPi - log(sdc64);
     const int K = min(P.K, n);
     const float* xa = P.xa_w + o0 * (D + 1);
-    int32_t status = 0;
+    const double wscale = N / ci->W;
+    if (tid == 0) {
+        s_status = 0;
+        s_resets = 0;
+    }
 
     // component k's FP32 density parameters from its FP64 weight, mean and
-    // covariance (floor where it does not factor); lane k only
-    auto set_comp = [&](int k, double w, const double (&mu)[D], const double (&S)[NT]) -> bool {
+    // covariance (floor where it does not factor); thread k only
+    auto set_comp = [&](int k, double w, const double (&mu)[D], const double (&S)[NT]) {
         CompState<float, D> cs;
 #pragma unroll
         for (int d = 0; d < D; ++d) cs.mu[d] = (float)mu[d];
 #pragma unroll
         for (int q = 0; q < NT; ++q) cs.S[q] = (float)S[q];
         cs.u = (float)w;
-        const bool fl = factor_comp<float, D>(cs, trC, sdc);
+        if (factor_comp<float, D>(cs, trC, sdc)) atomicOr(&s_status, GM_ST_COV_FLOOR);
         comp[k] = cs;
-        return fl;
     };
-    // theta of lane k from a weight, mean and (float) covariance
+    // theta of component k from a weight, mean and (float) covariance
     auto put_theta = [&](double* t, double w, const double (&mu)[D], const float (&S)[NT]) {
         t[0] = w;
 #pragma unroll
@@ -127,30 +140,30 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
             for (int j = i; j < D; ++j) t[1 + D + tri_idx<D>(i, j)] = (double)S[tri_idx<D>(i, j)] + mu[i] * mu[j];
     };
     auto wsum = [&](double x) -> double { return wave_sum(x); };
+    for (int t = tid; t < 2 * kMaxWaves * NKM; t += kStdThreads) red_d[t] = 0.0;
+    __syncthreads();
 
     // ---------------- start ------------------------------------------------
     const int32_t* idx = A.init_idx + (size_t)c * kInitSlots;
     if (P.kmeans) {
-        __shared__ double ctr[KMAX][D];
-        if (lane < K) {
-            const int ip = idx[lane];
+        if (tid < K) {
+            const int ip = idx[tid];
 #pragma unroll
-            for (int d = 0; d < D; ++d) ctr[lane][d] = A.v[(o0 + ip) * D + d] - ci->m[d];
+            for (int d = 0; d < D; ++d) ctr[tid][d] = A.v[(o0 + ip) * D + d] - ci->m[d];
         }
-        for (int i = lane; i < n; i += 64) P.assign[o0 + i] = -1;
+        for (int i = tid; i < n; i += kStdThreads) P.assign[o0 + i] = -1;
+        __syncthreads();
         int pass = 0;
         for (pass = 1; pass <= 100; ++pass) {
-            double acc[KMAX][1 + D];
+            double acc[NKM];
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-#pragma unroll
-                for (int t = 0; t < 1 + D; ++t) acc[k][t] = 0.0;
+            for (int t = 0; t < NKM; ++t) acc[t] = 0.0;
             int changed = 0;
-            for (int i = lane; i < n; i += 64) {
+            for (int i = tid; i < n; i += kStdThreads) {
                 double x[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) x[d] = A.v[(o0 + i) * D + d] - ci->m[d];
-                const double al = A.alpha[o0 + i] * (N / ci->W);
+                const double al = A.alpha[o0 + i] * wscale;
                 int best = 0;
                 double bd = INFINITY;
 #pragma unroll
@@ -172,74 +185,70 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
                     if (k == best) {
-                        acc[k][0] += al;
+                        acc[k * (1 + D)] += al;
 #pragma unroll
-                        for (int d = 0; d < D; ++d) acc[k][1 + d] += al * x[d];
+                        for (int d = 0; d < D; ++d) acc[k * (1 + D) + 1 + d] += al * x[d];
                     }
             }
-            if (__builtin_amdgcn_ballot_w64(changed != 0) == 0) break;
+            if (!__syncthreads_or(changed)) break;
+            block_sum<NKM, kStdWaves>(acc, red_d, par, kStdWaves);
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k < K) {
-                    double t[1 + D];
+            for (int k = 0; k < KMAX; ++k)
+                if (k == tid && k < K && acc[k * (1 + D)] > 0.0)
 #pragma unroll
-                    for (int q = 0; q < 1 + D; ++q) t[q] = wsum(acc[k][q]);
-                    if (lane == 0 && t[0] > 0.0)
-#pragma unroll
-                        for (int d = 0; d < D; ++d) ctr[k][d] = t[1 + d] / t[0];
-                }
-            }
+                    for (int d = 0; d < D; ++d) ctr[k][d] = acc[k * (1 + D) + 1 + d] / acc[k * (1 + D)];
             __syncthreads();
         }
         if (pass > 100) pass = 100;
-        if (P.kmeans_passes && lane == 0) P.kmeans_passes[c] = pass;
+        if (P.kmeans_passes && tid == 0) P.kmeans_passes[c] = pass;
         // the mixture of the hard assignment, one component per pass
         for (int k = 0; k < K; ++k) {
-            double wk = 0.0, cov[NT];
+            double vals[1 + NT];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) cov[q] = 0.0;
-            for (int i = lane; i < n; i += 64) {
+            for (int q = 0; q < 1 + NT; ++q) vals[q] = 0.0;
+            for (int i = tid; i < n; i += kStdThreads) {
                 if (P.assign[o0 + i] != k) continue;
-                const double al = A.alpha[o0 + i] * (N / ci->W);
+                const double al = A.alpha[o0 + i] * wscale;
                 double x[D];
 #pragma unroll
                 for (int d = 0; d < D; ++d) x[d] = A.v[(o0 + i) * D + d] - ci->m[d] - ctr[k][d];
-                wk += al;
+                vals[0] += al;
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int b = a; b < D; ++b) cov[tri_idx<D>(a, b)] += al * x[a] * x[b];
+                    for (int b = a; b < D; ++b) vals[1 + tri_idx<D>(a, b)] += al * x[a] * x[b];
             }
-            const double W = wsum(wk);
-            double S[NT], mu[D];
+            block_sum<NKM, kStdWaves>(vals, red_d, par, kStdWaves);
+            if (tid == k) {
+                const double W = vals[0];
+                double S[NT], mu[D];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                const double t = wsum(cov[q]);
-                S[q] = W > 0.0 ? t / W : 0.0;
-            }
+                for (int q = 0; q < NT; ++q) S[q] = W > 0.0 ? vals[1 + q] / W : 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) mu[d] = ctr[k][d];
-            if (lane == k) {
-                if (set_comp(k, W / N, mu, S)) status |= GM_ST_COV_FLOOR;
+                for (int d = 0; d < D; ++d) mu[d] = ctr[k][d];
+                set_comp(k, W / N, mu, S);
                 put_theta(th + k * L, W / N, mu, comp[k].S);
             }
         }
-    } else if (lane < K) {
-        const int ip = idx[lane];
+    } else if (tid < K) {
+        const int ip = idx[tid];
         double mu[D], S[NT];
 #pragma unroll
         for (int d = 0; d < D; ++d) mu[d] = A.v[(o0 + ip) * D + d] - ci->m[d];
 #pragma unroll
         for (int q = 0; q < NT; ++q) S[q] = ci->C[q];
-        if (set_comp(lane, 1.0 / K, mu, S)) status |= GM_ST_COV_FLOOR;
-        put_theta(th + lane * L, 1.0 / K, mu, comp[lane].S);
+        set_comp(tid, 1.0 / K, mu, S);
+        put_theta(th + tid * L, 1.0 / K, mu, comp[tid].S);
     }
     __syncthreads();
 
     // ---------------- iterations ---------------------------------------------
+    // every wave runs the E-step; wave 0 alone runs the parameter update and
+    // the mixing (lane k = component k) and publishes the control decision
     const int max_iter = A.max_sweeps;
     const double tol = A.tol;
-    int nh = 0, head = 0, resets = 0, it = 0;
+    const int mm = P.aa_m;
+    int nh = 0, head = 0, it = 0;
     bool mixed = false, have_prev = false, converged = false;
     double ll = 0.0, ll_prev = 0.0;
     while (it < max_iter) {
@@ -248,8 +257,8 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
         float sums[KMAX * NS];
 #pragma unroll
         for (int t = 0; t < KMAX * NS; ++t) sums[t] = 0.0f;
-        double lsum = 0.0;
-        for (int i = lane; i < n; i += 64) {
+        double lsum[1] = {0.0};
+        for (int i = tid; i < n; i += kStdThreads) {
             float x[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) x[d] = xa[(size_t)i * (D + 1) + d];
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
                 l[k] = k < K ? fast_exp2(l[k] - mx) : 0.0f;
                 s += l[k];
             }
-            lsum += (double)a * (double)(mx + fast_log2(s));
+            lsum[0] += (double)a * (double)(mx + fast_log2(s));
             const float inv = a * fast_rcp(s);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
@@ -288,223 +297,253 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
                 }
             }
         }
-        int par = 0;
-        em_block_sum<KMAX * NS, 1>(sums, (float*)nullptr, par, 1);
-        ll = kLn2 * wsum(lsum) + N * lnc0;
-        if (P.ll_trace && lane == 0) P.ll_trace[(size_t)c * max_iter + (it - 1)] = ll;
-        if (lane == 0)
+        // wave sums (the DPP tree of em_block_sum, every value level by level;
+        // lane 63 ends with the totals), then the waves' partials in wave order
 #pragma unroll
-            for (int t = 0; t < KMAX * NS; ++t) tot[t] = sums[t];
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0xB1>(sums[t]);
+#pragma unroll
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x4E>(sums[t]);
+#pragma unroll
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x141>(sums[t]);
+#pragma unroll
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x140>(sums[t]);
+#pragma unroll
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x142, 0xa>(sums[t]);
+#pragma unroll
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x143, 0xc>(sums[t]);
+        if (lane == 63)
+#pragma unroll
+            for (int t = 0; t < KMAX * NS; ++t) red_f[wid][t] = sums[t];
+        block_sum<NKM, kStdWaves>(lsum, red_d, par, kStdWaves);
+        for (int t = tid; t < KMAX * NS; t += kStdThreads) {
+            float v = red_f[0][t];
+#pragma unroll
+            for (int w = 1; w < kStdWaves; ++w) v += red_f[w][t];
+            tot[t] = v;
+        }
         __syncthreads();
+        ll = kLn2 * lsum[0] + N * lnc0;
+        if (P.ll_trace && tid == 0) P.ll_trace[(size_t)c * max_iter + (it - 1)] = ll;
 
-        const int mm = P.aa_m;
-        if (mixed && !(ll >= ll_prev)) {
-            // the mixed iterate lowered the likelihood: back to G of the last
-            // accepted iterate (the newest G of the ring), history cleared
-            ++resets;
-            if (lane < K) {
-                const double* gsrc = &Gh[(head + mm) % (mm + 1)][lane * L];
-                double mu[D], S[NT];
+        if (wid == 0) {
+            int ctl = 0;  // 0 go on, 1 converged, 2 stop (no finite likelihood), 3 rejected
+            if (mixed && !(ll >= ll_prev)) {
+                // the mixed iterate lowered the likelihood: back to G of the
+                // last accepted iterate (the newest G of the ring), history cleared
+                if (lane == 0) ++s_resets;
+                if (lane < K) {
+                    const double* gsrc = &Gh[(head + mm) % (mm + 1)][lane * L];
+                    double mu[D], S[NT];
 #pragma unroll
-                for (int d = 0; d < D; ++d) mu[d] = gsrc[1 + d];
+                    for (int d = 0; d < D; ++d) mu[d] = gsrc[1 + d];
 #pragma unroll
-                for (int i = 0; i < D; ++i)
+                    for (int i = 0; i < D; ++i)
 #pragma unroll
-                    for (int j = i; j < D; ++j) S[tri_idx<D>(i, j)] = gsrc[1 + D + tri_idx<D>(i, j)] - mu[i] * mu[j];
-                const double w = gsrc[0];
-                if (set_comp(lane, w, mu, S)) status |= GM_ST_COV_FLOOR;
-                put_theta(th + lane * L, w, mu, comp[lane].S);
-            }
-            nh = 0;
-            head = 0;
-            mixed = false;
-            __syncthreads();
-            continue;
-        }
-        if (have_prev && fabs(ll - ll_prev) <= tol * fabs(ll)) {
-            converged = true;
-            break;
-        }
-        if (!isfinite(ll)) break;
-        ll_prev = ll;
-        have_prev = true;
-
-        // G(theta): lane k forms component k's new weight, mean and covariance
-        // (a component without responsibility keeps its mean and covariance at
-        // weight 0)
-        double gmu[D], gS[NT], gw = 0.0, greg[L];
-        if (lane < K) {
-            const float* sk = tot + lane * NS;
-            const CompState<float, D> ck = comp[lane];
-            const double Nk = sk[0];
-            if (Nk > 0.0) {
-                double dl[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    dl[d] = (double)sk[1 + d] / Nk;
-                    gmu[d] = (double)ck.mu[d] + dl[d];
+                        for (int j = i; j < D; ++j)
+                            S[tri_idx<D>(i, j)] = gsrc[1 + D + tri_idx<D>(i, j)] - mu[i] * mu[j];
+                    const double w = gsrc[0];
+                    set_comp(lane, w, mu, S);
+                    put_theta(th + lane * L, w, mu, comp[lane].S);
                 }
-#pragma unroll
-                for (int i = 0; i < D; ++i)
-#pragma unroll
-                    for (int j = i; j < D; ++j)
-                        gS[tri_idx<D>(i, j)] = (double)sk[1 + D + tri_idx<D>(i, j)] / Nk - dl[i] * dl[j];
-                gw = Nk / N;
+                nh = 0;
+                head = 0;
+                mixed = false;
+                ctl = 3;
+            } else if (have_prev && fabs(ll - ll_prev) <= tol * fabs(ll)) {
+                ctl = 1;
+            } else if (!isfinite(ll)) {
+                ctl = 2;
             } else {
+                ll_prev = ll;
+                have_prev = true;
+                // G(theta): lane k forms component k's new weight, mean and
+                // covariance (a component without responsibility keeps its mean
+                // and covariance at weight 0)
+                double gmu[D], gS[NT], gw = 0.0, greg[L];
 #pragma unroll
-                for (int d = 0; d < D; ++d) gmu[d] = ck.mu[d];
+                for (int t = 0; t < L; ++t) greg[t] = 0.0;
+                if (lane < K) {
+                    const float* sk = tot + lane * NS;
+                    const CompState<float, D> ck = comp[lane];
+                    const double Nk = sk[0];
+                    if (Nk > 0.0) {
+                        double dl[D];
 #pragma unroll
-                for (int q = 0; q < NT; ++q) gS[q] = ck.S[q];
-                gw = 0.0;
-            }
-            greg[0] = gw;
-#pragma unroll
-            for (int d = 0; d < D; ++d) greg[1 + d] = gmu[d];
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int j = i; j < D; ++j) greg[1 + D + tri_idx<D>(i, j)] = gS[tri_idx<D>(i, j)] + gmu[i] * gmu[j];
-        }
-        bool take_g = true;
-        mixed = false;
-        if (mm > 0) {
-            // push (f_i, G_i)
-            if (lane < K)
-#pragma unroll
-                for (int t = 0; t < L; ++t) {
-                    Fh[head][lane * L + t] = greg[t] - th[lane * L + t];
-                    Gh[head][lane * L + t] = greg[t];
-                }
-            head = (head + 1) % (mm + 1);
-            if (nh < mm + 1) ++nh;
-            const int mk = nh - 1;
-            if (mk >= 1) {
-                const int cur = (head + mm) % (mm + 1);
-                // modified Gram-Schmidt on the differences of f, oldest first
-                double Rm[kStdAaMax][kStdAaMax], qf[kStdAaMax];
-                bool ok = true;
-                for (int j = 0; j < mk; ++j) {
-                    const int i0 = (head - nh + j + 2 * (mm + 1)) % (mm + 1);
-                    const int i1 = (i0 + 1) % (mm + 1);
-                    double qj[L], n0 = 0.0;
-#pragma unroll
-                    for (int t = 0; t < L; ++t) qj[t] = 0.0;
-                    if (lane < K)
-#pragma unroll
-                        for (int t = 0; t < L; ++t) {
-                            qj[t] = Fh[i1][lane * L + t] - Fh[i0][lane * L + t];
-                            n0 += qj[t] * qj[t];
+                        for (int d = 0; d < D; ++d) {
+                            dl[d] = (double)sk[1 + d] / Nk;
+                            gmu[d] = (double)ck.mu[d] + dl[d];
                         }
-                    n0 = wsum(n0);
-                    for (int l = 0; l < j; ++l) {
-                        double r = 0.0;
-                        if (lane < K)
-#pragma unroll
-                            for (int t = 0; t < L; ++t) r += Q[l][lane * L + t] * qj[t];
-                        r = wsum(r);
-                        Rm[l][j] = r;
-                        if (lane < K)
-#pragma unroll
-                            for (int t = 0; t < L; ++t) qj[t] -= r * Q[l][lane * L + t];
-                    }
-                    double nr = 0.0;
-                    if (lane < K)
-#pragma unroll
-                        for (int t = 0; t < L; ++t) nr += qj[t] * qj[t];
-                    nr = sqrt(wsum(nr));
-                    if (!(nr > 1e-12 * sqrt(n0))) {
-                        ok = false;
-                        break;
-                    }
-                    Rm[j][j] = nr;
-                    if (lane < K)
-#pragma unroll
-                        for (int t = 0; t < L; ++t) Q[j][lane * L + t] = qj[t] / nr;
-                }
-                if (ok) {
-                    for (int j = 0; j < mk; ++j) {
-                        double sq = 0.0;
-                        if (lane < K)
-#pragma unroll
-                            for (int t = 0; t < L; ++t) sq += Q[j][lane * L + t] * Fh[cur][lane * L + t];
-                        qf[j] = wsum(sq);
-                    }
-                    double gam[kStdAaMax];
-                    for (int j = mk - 1; j >= 0; --j) {
-                        double sq = qf[j];
-                        for (int l = j + 1; l < mk; ++l) sq -= Rm[j][l] * gam[l];
-                        gam[j] = sq / Rm[j][j];
-                    }
-                    // candidate G_i - dG gamma, weights renormalised
-                    double cand[L], w0 = 0.0;
-#pragma unroll
-                    for (int t = 0; t < L; ++t) cand[t] = 0.0;
-                    if (lane < K) {
-#pragma unroll
-                        for (int t = 0; t < L; ++t) {
-                            double sq = greg[t];
-                            for (int j = 0; j < mk; ++j) {
-                                const int i0 = (head - nh + j + 2 * (mm + 1)) % (mm + 1);
-                                const int i1 = (i0 + 1) % (mm + 1);
-                                sq -= gam[j] * (Gh[i1][lane * L + t] - Gh[i0][lane * L + t]);
-                            }
-                            cand[t] = sq;
-                        }
-                        w0 = cand[0];
-                    }
-                    const double ws = wsum(w0);
-                    // validity: weights >= 0, Sigma = M2 - mu mu^T positive definite
-                    bool valid = ws > 0.0;
-                    double cmu[D], cS[NT];
-                    if (lane < K) {
-                        cand[0] /= ws;
-#pragma unroll
-                        for (int d = 0; d < D; ++d) cmu[d] = cand[1 + d];
 #pragma unroll
                         for (int i = 0; i < D; ++i)
 #pragma unroll
                             for (int j = i; j < D; ++j)
-                                cS[tri_idx<D>(i, j)] = cand[1 + D + tri_idx<D>(i, j)] - cmu[i] * cmu[j];
-                        valid = valid && cand[0] >= 0.0 && spd64<D>(cS);
-                    }
-                    valid = __builtin_amdgcn_ballot_w64(!valid) == 0;
-                    if (valid) {
-                        if (lane < K) {
-                            if (set_comp(lane, cand[0], cmu, cS)) status |= GM_ST_COV_FLOOR;
+                                gS[tri_idx<D>(i, j)] = (double)sk[1 + D + tri_idx<D>(i, j)] / Nk - dl[i] * dl[j];
+                        gw = Nk / N;
+                    } else {
 #pragma unroll
-                            for (int t = 0; t < L; ++t) th[lane * L + t] = cand[t];
-                        }
-                        take_g = false;
-                        mixed = true;
+                        for (int d = 0; d < D; ++d) gmu[d] = ck.mu[d];
+#pragma unroll
+                        for (int q = 0; q < NT; ++q) gS[q] = ck.S[q];
+                        gw = 0.0;
                     }
+                    greg[0] = gw;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) greg[1 + d] = gmu[d];
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+#pragma unroll
+                        for (int j = i; j < D; ++j)
+                            greg[1 + D + tri_idx<D>(i, j)] = gS[tri_idx<D>(i, j)] + gmu[i] * gmu[j];
                 }
-                if (take_g) {
-                    // no usable mixed iterate: the history restarts from the latest pair
-                    ++resets;
-                    if (lane < K && cur != 0)
+                bool take_g = true;
+                mixed = false;
+                if (mm > 0) {
+                    // push (f_i, G_i)
+                    if (lane < K)
 #pragma unroll
                         for (int t = 0; t < L; ++t) {
-                            Fh[0][lane * L + t] = Fh[cur][lane * L + t];
-                            Gh[0][lane * L + t] = Gh[cur][lane * L + t];
+                            Fh[head][lane * L + t] = greg[t] - th[lane * L + t];
+                            Gh[head][lane * L + t] = greg[t];
                         }
-                    nh = 1;
-                    head = 1 % (mm + 1);
+                    head = (head + 1) % (mm + 1);
+                    if (nh < mm + 1) ++nh;
+                    const int mk = nh - 1;
+                    if (mk >= 1) {
+                        const int cur = (head + mm) % (mm + 1);
+                        // modified Gram-Schmidt on the differences of f, oldest first
+                        double Rm[kStdAaMax][kStdAaMax], qf[kStdAaMax];
+                        bool ok = true;
+                        for (int j = 0; j < mk; ++j) {
+                            const int i0 = (head - nh + j + 2 * (mm + 1)) % (mm + 1);
+                            const int i1 = (i0 + 1) % (mm + 1);
+                            double qj[L], n0 = 0.0;
+#pragma unroll
+                            for (int t = 0; t < L; ++t) qj[t] = 0.0;
+                            if (lane < K)
+#pragma unroll
+                                for (int t = 0; t < L; ++t) {
+                                    qj[t] = Fh[i1][lane * L + t] - Fh[i0][lane * L + t];
+                                    n0 += qj[t] * qj[t];
+                                }
+                            n0 = wsum(n0);
+                            for (int l = 0; l < j; ++l) {
+                                double r = 0.0;
+                                if (lane < K)
+#pragma unroll
+                                    for (int t = 0; t < L; ++t) r += Q[l][lane * L + t] * qj[t];
+                                r = wsum(r);
+                                Rm[l][j] = r;
+                                if (lane < K)
+#pragma unroll
+                                    for (int t = 0; t < L; ++t) qj[t] -= r * Q[l][lane * L + t];
+                            }
+                            double nr = 0.0;
+                            if (lane < K)
+#pragma unroll
+                                for (int t = 0; t < L; ++t) nr += qj[t] * qj[t];
+                            nr = sqrt(wsum(nr));
+                            if (!(nr > 1e-12 * sqrt(n0))) {
+                                ok = false;
+                                break;
+                            }
+                            Rm[j][j] = nr;
+                            if (lane < K)
+#pragma unroll
+                                for (int t = 0; t < L; ++t) Q[j][lane * L + t] = qj[t] / nr;
+                        }
+                        if (ok) {
+                            for (int j = 0; j < mk; ++j) {
+                                double sq = 0.0;
+                                if (lane < K)
+#pragma unroll
+                                    for (int t = 0; t < L; ++t) sq += Q[j][lane * L + t] * Fh[cur][lane * L + t];
+                                qf[j] = wsum(sq);
+                            }
+                            double gam[kStdAaMax];
+                            for (int j = mk - 1; j >= 0; --j) {
+                                double sq = qf[j];
+                                for (int l = j + 1; l < mk; ++l) sq -= Rm[j][l] * gam[l];
+                                gam[j] = sq / Rm[j][j];
+                            }
+                            // candidate G_i - dG gamma, weights renormalised
+                            double cand[L], w0 = 0.0;
+#pragma unroll
+                            for (int t = 0; t < L; ++t) cand[t] = 0.0;
+                            if (lane < K) {
+#pragma unroll
+                                for (int t = 0; t < L; ++t) {
+                                    double sq = greg[t];
+                                    for (int j = 0; j < mk; ++j) {
+                                        const int i0 = (head - nh + j + 2 * (mm + 1)) % (mm + 1);
+                                        const int i1 = (i0 + 1) % (mm + 1);
+                                        sq -= gam[j] * (Gh[i1][lane * L + t] - Gh[i0][lane * L + t]);
+                                    }
+                                    cand[t] = sq;
+                                }
+                                w0 = cand[0];
+                            }
+                            const double ws = wsum(w0);
+                            // validity: weights >= 0, Sigma = M2 - mu mu^T positive definite
+                            bool valid = ws > 0.0;
+                            double cmu[D], cS[NT];
+                            if (lane < K) {
+                                cand[0] /= ws;
+#pragma unroll
+                                for (int d = 0; d < D; ++d) cmu[d] = cand[1 + d];
+#pragma unroll
+                                for (int i = 0; i < D; ++i)
+#pragma unroll
+                                    for (int j = i; j < D; ++j)
+                                        cS[tri_idx<D>(i, j)] = cand[1 + D + tri_idx<D>(i, j)] - cmu[i] * cmu[j];
+                                valid = valid && cand[0] >= 0.0 && spd64<D>(cS);
+                            }
+                            valid = __builtin_amdgcn_ballot_w64(!valid) == 0;
+                            if (valid) {
+                                if (lane < K) {
+                                    set_comp(lane, cand[0], cmu, cS);
+#pragma unroll
+                                    for (int t = 0; t < L; ++t) th[lane * L + t] = cand[t];
+                                }
+                                take_g = false;
+                                mixed = true;
+                            }
+                        }
+                        if (take_g) {
+                            // no usable mixed iterate: the history restarts from the latest pair
+                            if (lane == 0) ++s_resets;
+                            if (lane < K && cur != 0)
+#pragma unroll
+                                for (int t = 0; t < L; ++t) {
+                                    Fh[0][lane * L + t] = Fh[cur][lane * L + t];
+                                    Gh[0][lane * L + t] = Gh[cur][lane * L + t];
+                                }
+                            nh = 1;
+                            head = 1 % (mm + 1);
+                        }
+                    }
+                }
+                if (take_g && lane < K) {
+                    set_comp(lane, gw, gmu, gS);
+                    put_theta(th + lane * L, gw, gmu, comp[lane].S);
                 }
             }
-        }
-        if (take_g && lane < K) {
-            if (set_comp(lane, gw, gmu, gS)) status |= GM_ST_COV_FLOOR;
-            put_theta(th + lane * L, gw, gmu, comp[lane].S);
+            if (lane == 0) s_ctl = ctl;
         }
         __syncthreads();
+        const int ctl = s_ctl;
+        __syncthreads();  // s_ctl is rewritten in the next iteration
+        if (ctl == 1) {
+            converged = true;
+            break;
+        }
+        if (ctl == 2) break;
     }
-    if (!converged) status |= GM_ST_MAXSWEEPS;
 
     // ---------------- state into the output record --------------------------
     // components left without weight are dropped, the others renormalised
     __shared__ int s_slot[KMAX];
     __shared__ double s_wsum;
-    if (lane == 0) {
+    if (tid == 0) {
         int kk = 0;
         double ws = 0.0;
         for (int k = 0; k < K; ++k) {
@@ -517,14 +556,14 @@ __global__ __launch_bounds__(64) void k_std(StdArgs P)
         A.out.L_pen[c] = ll;
         A.out.sweeps[c] = it;
         A.out.visits[c] = (int64_t)it * K;
-        A.out.status[c] = status;
-        if (P.resets) P.resets[c] = resets;
+        A.out.status[c] = s_status | (converged ? 0 : GM_ST_MAXSWEEPS);
+        if (P.resets) P.resets[c] = s_resets;
     }
     __syncthreads();
-    if (lane < K && s_slot[lane] >= 0) {
-        const size_t sk = (size_t)c * A.kmax + s_slot[lane];
-        const CompState<float, D> cs = comp[lane];
-        A.out.omega[sk] = th[lane * L] / s_wsum;
+    if (tid < K && s_slot[tid] >= 0) {
+        const size_t sk = (size_t)c * A.kmax + s_slot[tid];
+        const CompState<float, D> cs = comp[tid];
+        A.out.omega[sk] = th[tid * L] / s_wsum;
         for (int d = 0; d < D; ++d) A.out.mu[sk * D + d] = (double)cs.mu[d];
         for (int q = 0; q < NT; ++q) A.out.sigma[sk * NT + q] = (double)cs.S[q];
     }
@@ -536,9 +575,9 @@ int launch_std_d(const StdArgs& p, int64_t n_cells, hipStream_t st)
     if (n_cells == 0) return 0;
     hipLaunchKernelGGL(k_std_stage<D>, dim3((unsigned)n_cells), dim3(256), 0, st, p);
     if (p.a.kmax <= 8)
-        hipLaunchKernelGGL((k_std<D, 8>), dim3((unsigned)n_cells), dim3(64), 0, st, p);
+        hipLaunchKernelGGL((k_std<D, 8>), dim3((unsigned)n_cells), dim3(kStdThreads), 0, st, p);
     else
-        hipLaunchKernelGGL((k_std<D, 16>), dim3((unsigned)n_cells), dim3(64), 0, st, p);
+        hipLaunchKernelGGL((k_std<D, 16>), dim3((unsigned)n_cells), dim3(kStdThreads), 0, st, p);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
