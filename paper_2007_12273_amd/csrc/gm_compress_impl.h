@@ -400,7 +400,8 @@ __device__ __forceinline__ T dpp_get(T x)
 // Workgroup sum of the NV M-step sums of one component update, delivered to
 // every thread.  The 64-lane tree of wave_sum is applied to all NV values one
 // level at a time, so the independent DPP operations fill each other's wait
-// states.  Lane 0 of every wave publishes its wave's sums; after one barrier
+// states.  Lane 63 of every wave, where the tree ends, publishes its wave's
+// sums; after one barrier
 // lane v < NV adds value v over all MAXW slots in wave order: slots of absent
 // waves hold zeros (the buffer is cleared when the kernel starts and only
 // present waves write), so no per-wave test is needed.  The additions happen
@@ -420,12 +421,15 @@ __device__ __forceinline__ void em_block_sum(T (&x)[NV], T* buf, int& parity, in
     for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142, 0xa>(x[v]);  // row_bcast:15
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143, 0xc>(x[v]);  // row_bcast:31
+    if (nwaves == 1) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);
-    if (nwaves == 1) return;
+        for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);
+        return;
+    }
+    // lane 63 holds the wave's sums
     T* b = buf + parity * (MAXW * NVMAX);
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) b[wid * NVMAX + v] = x[v];
     }
@@ -518,6 +522,9 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
         const double sdc64 = sqrt_det<D>(ci->C);
         const R sdc = (R)sdc64;
         const double lnc0 = -0.5 * D * kLnTwoPi - log(sdc64);
+        const double lnN = log((double)n);
+        int K_den = -1;
+        R inv_den = R(0);
         const int64_t o0 = A.off[c];
         const double* vc = A.v + o0 * D;
         const int kmax = A.kmax;
@@ -799,7 +806,11 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
 #pragma unroll
                             for (int j = i; j < D; ++j)
                                 cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
-                        const R wk = NkT * m_rcp((R)(N - halfT * K));
+                        if (K != K_den) {  // 1 / (N - T K / 2), recomputed when K changes
+                            inv_den = m_rcp((R)(N - halfT * K));
+                            K_den = K;
+                        }
+                        const R wk = NkT * inv_den;
                         const R unew = wk * G;
                         G = G - cku + unew;
                         cn.u = unew;
@@ -894,16 +905,26 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                         comp[lane].u = comp[lane].u * m_rcp(G);
                         comp[lane].c2 = comp[lane].c2 - lg2G;
                     }
-                    R Gn = R(0);
-                    double pen = 0.0;
-                    for (int j = 0; j < Kslots; ++j)
-                        if ((alive >> j) & 1u) Gn += comp[j].u;
-                    for (int j = 0; j < Kslots; ++j)
-                        if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u / Gn);
+                    // G = sum_j u_j and sum_j log2(u_j / G) over the live slots, lane j
+                    // holding slot j (a 16-lane tree, then broadcast from lane 0)
+                    const bool live_lane = lane < Kslots && ((alive >> lane) & 1u);
+                    R uj = live_lane ? comp[lane].u : R(0);
+                    R Gn = uj;
+                    Gn += dpp_get<0xB1>(Gn);
+                    Gn += dpp_get<0x4E>(Gn);
+                    Gn += dpp_get<0x141>(Gn);
+                    Gn += dpp_get<0x140>(Gn);
+                    Gn = lane_bcast(Gn, 0);
+                    double pl = live_lane ? (double)fast_log2(uj * m_rcp(Gn)) : 0.0;
+                    pl += dpp_get<0xB1>(pl);
+                    pl += dpp_get<0x4E>(pl);
+                    pl += dpp_get<0x141>(pl);
+                    pl += dpp_get<0x140>(pl);
+                    const double pen = lane_bcast(pl, 0);
                     G = Gn;
                     const double dpar = K * T + K - 1;
                     // ref_p is log2 of the mixture density relative to (2 pi)^(-D/2) / sqrt det C
-                    L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * log(N);
+                    L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * lnN;
 
                     // ---- compaction of dead slots (rare) ----
                     if (annihilated) {
