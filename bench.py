@@ -91,7 +91,7 @@ def parse():
                    help="warm: learned warm start (the headline); cold: plain EM only")
     p.add_argument("--train-sets", type=int, default=16, help="training batches of cells (seeds 5000+i)")
     p.add_argument("--epochs", type=int, default=50)
-    p.add_argument("--cpu-cells", type=int, default=4096, help="cells in the CPU-oracle sample (all cells of the Weibel-like workload: several seconds on 16 host threads)")
+    p.add_argument("--cpu-cells", type=int, default=512, help="cells in the CPU-oracle sample (512 evenly spaced cells of the Weibel-like batch: about 15 s on 16 host threads)")
     p.add_argument("--no-outer", action="store_true", help="skip the outer-search-over-K measurement")
     p.add_argument("--no-standard", action="store_true", help="skip the standard-EM (K-means, Anderson) measurement")
     p.add_argument("--no-cpu-baseline", action="store_true")
