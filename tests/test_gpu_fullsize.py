@@ -295,3 +295,43 @@ def test_restart_chain_full_size():
         assert frac >= (0.97 if name == "weibel_3v" else 0.9)
         del v, a, off, r, rec, out, x0
         torch.cuda.empty_cache()
+
+
+def test_weibel_full_size_standard_em_and_outer_search():
+    """The standard EM (K = 8, Anderson memory 5, random and K-means starts)
+    and the outer search over K on the full Weibel-like batch, in the
+    benchmark's launch configuration: sampled cells against the oracle
+    (standard EM: where both reach the same maximum, parameters to the
+    converged-mode bars; outer search: K and L), every cell's moments."""
+    from paper_2007_12273_amd import api
+    from gpu_util import mixture_errors
+    d = synth.make("weibel_3v")
+    n_cells = len(d["cell_off"]) - 1
+    v, a, off = to_gpu(d)
+    cells = _weibel_samples(n_cells)
+    vs, al, so = _sample_batch(d, cells)
+    for km in (False, True):
+        s = api.StandardEM(n_cells, len(d["alpha"]), 3, 16, device=dev(), seed=2003)
+        g = host(s(v, a, off, 8, kmeans=km, aa_memory=5).as_dict())
+        _all_cells_conserve(g, 3)
+        o = oracle.compress_std(vs, al, so, 8, seed=2003, kmax=16, kmeans=km, aa_m=5)
+        same = [c for c in cells if abs(g["L_pen"][c] - o["ll"][c]) <= 1e-5 * abs(o["ll"][c])]
+        errs = [max(mixture_errors(g, o, c, 3)) for c in same if g["K"][c] == o["K"][c]]
+        print("standard EM (%s start): same maximum in %d / %d sampled cells, parameter error median %.1e max %.1e"
+              % ("K-means" if km else "random", len(same), len(cells), np.median(errs), np.max(errs)))
+        assert len(same) >= 0.7 * len(cells)
+        # the oracle's own parameters move by a median 2e-3 (90% within
+        # 1.4e-2) between its stop at 1e-7 and a stop at 1e-9 with eight
+        # components on these cells (test_standard_em_stop_rule_resolution)
+        assert np.median(errs) <= 5e-3 and (np.array(errs) <= 3e-2).mean() >= 0.9
+        for c in cells:
+            assert np.abs(g["moments"][c] - o["moments"][c]).max() <= 1e-12 * np.abs(o["moments"][c]).max()
+    comp = api.Compressor(n_cells, 3, 16, device=dev(), seed=2003, outer_k=True)
+    g = host(comp(v, a, off).as_dict())
+    _all_cells_conserve(g, 3)
+    o = oracle.compress(vs, al, so, kmax=16, seed=2003, mode=oracle.MODE_OUTER_K)
+    kk = np.array([g["K"][c] == o["K"][c] for c in cells])
+    eL = np.array([abs(g["L_pen"][c] - o["L_pen"][c]) / abs(o["L_pen"][c]) for c in cells])
+    print("outer search: K equal in %d / %d sampled cells, L error median %.1e" % (kk.sum(), len(cells),
+                                                                                  np.median(eL[kk])))
+    assert kk.mean() >= 0.85 and (eL[kk] <= 1e-4).mean() >= 0.9
