@@ -32,9 +32,13 @@
 //   A_j  = sqrt(log2(e)/2) L_j^{-1},   Sigma_j = L_j L_j^T,
 // with u_j unnormalised weights (G = sum u_j).  A component update costs one
 // exp2 per particle; the denominator sum_j e_pj is updated by the change of
-// the one term, re-summed exactly where most of it cancelled and at the end
-// of every sweep, where ref_p + log2(sum_j e_pj) - log2 G is the particle's
-// log2 mixture density, the per-particle term of eq. (lnL-GM).  A particle
+// the one term and re-summed exactly where most of it cancelled.  At the end
+// of a sweep ref_p + log2(sum_j e_pj) - log2 G is the particle's log2
+// mixture density, the per-particle term of eq. (lnL-GM); the sum is exact
+// there (from the stored terms in the register-resident buckets, recomputed
+// every fourth sweep and after an annihilation in the others, which close
+// the remaining sweeps with the running sum, accurate to a few FP32 ulps of
+// the particle's density).  A particle
 // whose sum underflows, or whose new term overflows the reference, is
 // rebased: its terms are recomputed about their own maximum (a log2-space
 // log-sum-exp).
@@ -387,6 +391,10 @@ __device__ __forceinline__ R log2_term(const CompState<R, D>& cs, const R (&x)[D
 }
 
 constexpr int kEmMaxWaves = kEmMaxThreads / 64;
+// recomputed-density buckets re-sum every particle's density terms exactly
+// every kResumSweeps sweeps (and after a sweep with an annihilation); in the
+// other sweeps the running sums close the sweep
+constexpr int kResumSweeps = 4;
 
 template <int CTRL, int ROW_MASK = 0xf, typename T>
 __device__ __forceinline__ T dpp_get(T x)
@@ -857,9 +865,15 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                     if constexpr (STORE_E) {
 #pragma unroll
                         for (int p = 0; p < P; ++p) dens[p] = resum(e[p]);
+                    } else if (s % kResumSweeps != 0 && !annihilated) {
+                        // the running sums, kept through the sweep's updates
+                        // (each re-summed exactly where it had cancelled)
+#pragma unroll
+                        for (int p = 0; p < P; ++p) dens[p] = Sden[p];
                     } else {
-                        // component outer, particles inner: each component's
-                        // parameters are read from LDS once per sweep
+                        // exact re-sum every kResumSweeps sweeps and after an
+                        // annihilation: component outer, particles inner, each
+                        // component's parameters read from LDS once
 #pragma unroll
                         for (int p = 0; p < P; ++p) dens[p] = R(0);
                         for (int j = 0; j < Kslots; ++j) {
