@@ -155,8 +155,10 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
  * persistent launch whose workgroups take cells from a queue, spread over
  * the caller's stream and three library streams.  A bucket can run with
  * several launch variants: particles per thread (1, 2, 4, 8, 16), the
- * matching number of 64-lane waves per workgroup, and density terms kept
- * in registers or recomputed.  gm_autotune measures, on the caller's batch,
+ * matching number of 64-lane waves per workgroup, density terms kept in
+ * registers or recomputed, and the standard build (up to 8 waves per
+ * workgroup, up to 256 VGPRs per lane) or, for FP32 iterations, the lean
+ * build (up to 16 waves, at most 128 VGPRs: twice the waves per SIMD).  gm_autotune measures, on the caller's batch,
  * every non-empty bucket alone under each variant, keeps the fastest per
  * bucket, assigns the buckets to the four streams longest first onto the
  * least-loaded stream, times the concurrent EM phase of that plan against
@@ -170,8 +172,9 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
  * report: nullable, at least GM_TUNE_REPORT_LEN doubles: [0] EM phase of
  * the built-in plan (ms), [1] of the tuned plan, [2 + b] bucket b's
  * fastest standalone time (0 when empty), [14 + b] the installed variant of
- * bucket b as per_thread * 100 + waves * 10 + (1 if register-resident),
- * [26 + b] its stream (0-2 library streams, 3 the caller's). */
+ * bucket b as per_thread * 1000 + waves * 10 + mode, mode = (1 if
+ * register-resident) + (2 if lean), [26 + b] its stream (0-2 library
+ * streams, 3 the caller's). */
 #define GM_TUNE_REPORT_LEN 38
 int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
                 const gm_opts* o, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,
@@ -180,7 +183,10 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
 /* Install a plan by hand for (D, kmax class, fp64, warm): variant[b] and
  * (nullable) lane[b] for the twelve buckets, coded as in the report; a
  * variant must be built (see above) and cover the bucket: 64 * per_thread *
- * waves >= the bucket's largest cell, waves <= 8.  GM_EINVAL otherwise. */
+ * waves >= the bucket's largest cell, waves <= 8 (16 for lean builds).
+ * Built: standard 1, 2, 4 register-resident (8 at kmax <= 8) and 8, 16
+ * recomputed; lean (FP32 only) 1, 2 register-resident and 4, 8 recomputed.
+ * GM_EINVAL otherwise. */
 int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant,
                     const int32_t* lane);
 

@@ -7,14 +7,14 @@
 #include <algorithm>
 
 namespace gm {
-int launch_compress_d1_float(int, int, bool, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d3_float(int, int, bool, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d1_double(int, int, bool, int, const CompressArgs&, int, hipStream_t);
-int launch_compress_d3_double(int, int, bool, int, const CompressArgs&, int, hipStream_t);
-int grid_compress_d1_float(int, int, bool, int);
-int grid_compress_d3_float(int, int, bool, int);
-int grid_compress_d1_double(int, int, bool, int);
-int grid_compress_d3_double(int, int, bool, int);
+int launch_compress_d1_float(int, int, int, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d3_float(int, int, int, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d1_double(int, int, int, int, const CompressArgs&, int, hipStream_t);
+int launch_compress_d3_double(int, int, int, int, const CompressArgs&, int, hipStream_t);
+int grid_compress_d1_float(int, int, int, int);
+int grid_compress_d3_float(int, int, int, int);
+int grid_compress_d1_double(int, int, int, int);
+int grid_compress_d3_double(int, int, int, int);
 int launch_compress_pre_d1(const CompressArgs&, hipStream_t);
 int launch_compress_pre_d3(const CompressArgs&, hipStream_t);
 int launch_compress_requeue_d1(const CompressArgs&, hipStream_t);
@@ -94,7 +94,7 @@ Fork* fork_for_device()
 // template, precision, warm or cold start) with measured choices.
 struct EmPlan {
     int8_t per_thread[gm::kNumBuckets];
-    int8_t store_e[gm::kNumBuckets];
+    int8_t mode[gm::kNumBuckets];  // gm::kModeStoreE | gm::kModeLean
     int8_t waves[gm::kNumBuckets];
     int8_t lane[gm::kNumBuckets];
     int8_t order[gm::kNumBuckets];  // launch order, first launched first
@@ -107,7 +107,7 @@ EmPlan default_plan(int kt)
     for (int b = 0; b < gm::kNumBuckets; ++b) {
         const gm::Bucket& c = gm::bucket_cfg(kt, b);
         p.per_thread[b] = (int8_t)c.per_thread;
-        p.store_e[b] = c.store_e ? 1 : 0;
+        p.mode[b] = (int8_t)(c.store_e ? gm::kModeStoreE : 0);
         p.waves[b] = (int8_t)c.waves;
         p.lane[b] = (int8_t)(kt == 8 ? kBucketLane8[b] : kBucketLane16[b]);
         p.order[b] = (int8_t)(gm::kNumBuckets - 1 - b);  // largest cells first
@@ -133,21 +133,21 @@ int launch_em_bucket(int D, bool fp64, int kt, int b, const EmPlan& p, gm::Compr
                      hipStream_t st)
 {
     const int P = p.per_thread[b], W = p.waves[b];
-    const bool se = p.store_e[b] != 0;
+    const int mode = p.mode[b];
     int grid = 0;
     if (D == 1)
-        grid = fp64 ? gm::grid_compress_d1_double(kt, P, se, W) : gm::grid_compress_d1_float(kt, P, se, W);
+        grid = fp64 ? gm::grid_compress_d1_double(kt, P, mode, W) : gm::grid_compress_d1_float(kt, P, mode, W);
     else
-        grid = fp64 ? gm::grid_compress_d3_double(kt, P, se, W) : gm::grid_compress_d3_float(kt, P, se, W);
+        grid = fp64 ? gm::grid_compress_d3_double(kt, P, mode, W) : gm::grid_compress_d3_float(kt, P, mode, W);
     if (grid < 1) return -1;
     if ((int64_t)grid > n_cells) grid = (int)n_cells;
     a.bucket = b;
     a.nwaves = W;
     if (D == 1)
-        return fp64 ? gm::launch_compress_d1_double(kt, P, se, W, a, grid, st)
-                    : gm::launch_compress_d1_float(kt, P, se, W, a, grid, st);
-    return fp64 ? gm::launch_compress_d3_double(kt, P, se, W, a, grid, st)
-                : gm::launch_compress_d3_float(kt, P, se, W, a, grid, st);
+        return fp64 ? gm::launch_compress_d1_double(kt, P, mode, W, a, grid, st)
+                    : gm::launch_compress_d1_float(kt, P, mode, W, a, grid, st);
+    return fp64 ? gm::launch_compress_d3_double(kt, P, mode, W, a, grid, st)
+                : gm::launch_compress_d3_float(kt, P, mode, W, a, grid, st);
 }
 
 // the EM phase: fork onto the lanes, launch every bucket in plan order, join
@@ -395,8 +395,9 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
         for (int vi = 0; vi < gm::kNumVariants; ++vi) {
             const gm::EmVariant& var = gm::kVariants[vi];
             if (var.store_e && var.per_thread == 8 && kt != 8) continue;
+            if (var.lean && fp64) continue;
             const int waves = (max_n + 64 * var.per_thread - 1) / (64 * var.per_thread);
-            if (waves < 1 || waves > gm::kEmMaxWaves) continue;
+            if (waves < 1 || waves > gm::em_max_waves(var.lean)) continue;
             cand[b][ncand[b]][0] = vi;
             cand[b][ncand[b]][1] = waves;
             ++ncand[b];
@@ -410,10 +411,12 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     int rc = GM_OK;
     double best_ms[gm::kNumBuckets];
     int best_c[gm::kNumBuckets];
+    double lean_ms[gm::kNumBuckets];  // fastest lean-build candidate
+    int lean_c[gm::kNumBuckets];
     EmPlan trial = default_plan(kt);
     for (int b = 0; b < gm::kNumBuckets; ++b) {
-        best_ms[b] = 0.0;
-        best_c[b] = -1;
+        best_ms[b] = lean_ms[b] = 0.0;
+        best_c[b] = lean_c[b] = -1;
     }
     // every bucket alone on the device, once per candidate
     for (int r = 0; r < maxc && rc == GM_OK; ++r) {
@@ -423,7 +426,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
             if (counts[b] <= 0 || r >= ncand[b]) continue;
             const gm::EmVariant& var = gm::kVariants[cand[b][r][0]];
             trial.per_thread[b] = (int8_t)var.per_thread;
-            trial.store_e[b] = var.store_e ? 1 : 0;
+            trial.mode[b] = (int8_t)((var.store_e ? gm::kModeStoreE : 0) | (var.lean ? gm::kModeLean : 0));
             trial.waves[b] = (int8_t)cand[b][r][1];
             if (hipEventRecord(ev[2 * b], st) != hipSuccess ||
                 launch_em_bucket(D, fp64, kt, b, trial, a, n_cells, st) ||
@@ -443,39 +446,57 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
                 best_ms[b] = t;
                 best_c[b] = r;
             }
+            if (gm::kVariants[cand[b][r][0]].lean && (lean_c[b] < 0 || t < lean_ms[b])) {
+                lean_ms[b] = t;
+                lean_c[b] = r;
+            }
         }
     }
-    // tuned plan: fastest variant per bucket; buckets spread over the lanes
-    // longest first onto the least-loaded lane, and launched in that order
-    EmPlan tuned = default_plan(kt);
-    if (rc == GM_OK) {
+    // A tuned plan from a choice of candidate per bucket: buckets spread
+    // over the lanes longest first onto the least-loaded lane, and launched
+    // in that order.  Two choices: the fastest variant alone, and the
+    // fastest lean-build variant where the bucket has one.  Alone, a bucket
+    // has the device to itself; in the concurrent phase the lean builds
+    // leave room on a CU for the other buckets' workgroups, which can beat
+    // a variant that is faster alone.
+    auto make_plan = [&](const int* choice, const double* ms) {
+        EmPlan t = default_plan(kt);
         int idx[gm::kNumBuckets];
         for (int b = 0; b < gm::kNumBuckets; ++b) {
             idx[b] = b;
-            if (best_c[b] >= 0) {
-                const gm::EmVariant& var = gm::kVariants[cand[b][best_c[b]][0]];
-                tuned.per_thread[b] = (int8_t)var.per_thread;
-                tuned.store_e[b] = var.store_e ? 1 : 0;
-                tuned.waves[b] = (int8_t)cand[b][best_c[b]][1];
+            if (choice[b] >= 0) {
+                const gm::EmVariant& var = gm::kVariants[cand[b][choice[b]][0]];
+                t.per_thread[b] = (int8_t)var.per_thread;
+                t.mode[b] = (int8_t)((var.store_e ? gm::kModeStoreE : 0) | (var.lean ? gm::kModeLean : 0));
+                t.waves[b] = (int8_t)cand[b][choice[b]][1];
             }
         }
-        std::stable_sort(idx, idx + gm::kNumBuckets, [&](int x, int y) { return best_ms[x] > best_ms[y]; });
+        std::stable_sort(idx, idx + gm::kNumBuckets, [&](int x, int y) { return ms[x] > ms[y]; });
         double load[kLanes] = {0, 0, 0, 0};
         for (int i = 0; i < gm::kNumBuckets; ++i) {
             const int b = idx[i];
             int l = 0;
             for (int q = 1; q < kLanes; ++q)
                 if (load[q] < load[l]) l = q;
-            tuned.lane[b] = (int8_t)l;
-            load[l] += best_ms[b];
-            tuned.order[i] = (int8_t)b;
+            t.lane[b] = (int8_t)l;
+            load[l] += ms[b];
+            t.order[i] = (int8_t)b;
         }
-        tuned.tuned = true;
+        t.tuned = true;
+        return t;
+    };
+    int pref_c[gm::kNumBuckets];
+    double pref_ms[gm::kNumBuckets];
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        const bool lean = lean_c[b] >= 0;
+        pref_c[b] = lean ? lean_c[b] : best_c[b];
+        pref_ms[b] = lean ? lean_ms[b] : best_ms[b];
     }
-    // keep whichever plan runs the concurrent phase faster
-    double phase_ms[2] = {0.0, 0.0};
-    const EmPlan cands[2] = {default_plan(kt), tuned};
-    for (int pi = 0; pi < 2 && rc == GM_OK; ++pi) {
+    // keep whichever plan runs the concurrent phase fastest
+    constexpr int kPlans = 3;
+    double phase_ms[kPlans] = {0.0, 0.0, 0.0};
+    const EmPlan cands[kPlans] = {default_plan(kt), make_plan(best_c, best_ms), make_plan(pref_c, pref_ms)};
+    for (int pi = 0; pi < kPlans && rc == GM_OK; ++pi) {
         double best = 1e30;
         for (int rep = 0; rep < 2 && rc == GM_OK; ++rep) {
             float t = 0.f;
@@ -487,7 +508,10 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
         }
         phase_ms[pi] = best;
     }
-    const EmPlan& chosen = (rc == GM_OK && phase_ms[1] < phase_ms[0]) ? cands[1] : cands[0];
+    int pick = 0;
+    for (int pi = 1; pi < kPlans; ++pi)
+        if (phase_ms[pi] < phase_ms[pick]) pick = pi;
+    const EmPlan& chosen = cands[rc == GM_OK ? pick : 0];
     if (rc == GM_OK) {
         EmPlan* slot = plan_slot(D, kt, fp64, warm, true);
         if (!slot) rc = GM_EHIP;
@@ -501,11 +525,11 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     for (int i = 0; i < 2 * gm::kNumBuckets; ++i) (void)hipEventDestroy(ev[i]);
     if (rc == GM_OK && report) {
         report[0] = phase_ms[0];
-        report[1] = phase_ms[1];
+        report[1] = std::min(phase_ms[1], phase_ms[2]);
         for (int b = 0; b < gm::kNumBuckets; ++b) {
             report[2 + b] = best_ms[b];
             report[2 + gm::kNumBuckets + b] =
-                chosen.per_thread[b] * 100 + chosen.waves[b] * 10 + (chosen.store_e[b] ? 1 : 0);
+                gm::em_variant_code(chosen.per_thread[b], chosen.waves[b], chosen.mode[b]);
             report[2 + 2 * gm::kNumBuckets + b] = chosen.lane[b];
         }
     }
@@ -519,16 +543,18 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
     EmPlan p = default_plan(kt);
     for (int b = 0; b < gm::kNumBuckets; ++b) {
         const int code = variant[b];
-        const int P = code / 100, W = (code / 10) % 10;
-        const bool se = (code % 10) != 0;
+        const int P = code / 1000, W = (code / 10) % 100, mode = code % 10;
+        if (code < 0 || mode > (gm::kModeStoreE | gm::kModeLean)) return GM_EINVAL;
+        const bool se = (mode & gm::kModeStoreE) != 0, lean = (mode & gm::kModeLean) != 0;
         bool known = false;
         for (int vi = 0; vi < gm::kNumVariants; ++vi)
-            known |= gm::kVariants[vi].per_thread == P && gm::kVariants[vi].store_e == se;
-        if (!known || (se && P == 8 && kt != 8) || (code % 10) > 1) return GM_EINVAL;
-        if (W < 1 || W > gm::kEmMaxWaves || 64 * P * W < gm::bucket_cfg(kt, b).max_n) return GM_EINVAL;
+            known |= gm::kVariants[vi].per_thread == P && gm::kVariants[vi].store_e == se &&
+                     gm::kVariants[vi].lean == lean;
+        if (!known || (se && P == 8 && kt != 8) || (lean && fp64)) return GM_EINVAL;
+        if (W < 1 || W > gm::em_max_waves(lean) || 64 * P * W < gm::bucket_cfg(kt, b).max_n) return GM_EINVAL;
         p.per_thread[b] = (int8_t)P;
         p.waves[b] = (int8_t)W;
-        p.store_e[b] = se ? 1 : 0;
+        p.mode[b] = (int8_t)mode;
         if (lane) {
             if (lane[b] < 0 || lane[b] >= kLanes) return GM_EINVAL;
             p.lane[b] = (int8_t)lane[b];

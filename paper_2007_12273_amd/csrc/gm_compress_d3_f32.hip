@@ -3,15 +3,15 @@
 
 namespace gm {
 
-int launch_compress_d3_float(int kmax_tpl, int per_thread, bool store_e, int waves, const CompressArgs& a, int grid,
+int launch_compress_d3_float(int kmax_tpl, int per_thread, int mode, int waves, const CompressArgs& a, int grid,
                           hipStream_t st)
 {
-    return launch_bucket_dr<3, float>(kmax_tpl, per_thread, store_e, waves, a, grid, st);
+    return launch_bucket_dr<3, float>(kmax_tpl, per_thread, mode, waves, a, grid, st);
 }
 
-int grid_compress_d3_float(int kmax_tpl, int per_thread, bool store_e, int waves)
+int grid_compress_d3_float(int kmax_tpl, int per_thread, int mode, int waves)
 {
-    return grid_dr<3, float>(kmax_tpl, per_thread, store_e, waves);
+    return grid_dr<3, float>(kmax_tpl, per_thread, mode, waves);
 }
 
 int launch_compress_pre_d3(const CompressArgs& a, hipStream_t st) { return launch_pre_dr<3>(a, st); }

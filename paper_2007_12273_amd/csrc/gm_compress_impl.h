@@ -390,7 +390,6 @@ __device__ __forceinline__ R log2_term(const CompState<R, D>& cs, const R (&x)[D
     return cs.c2 - tri_quad<D, R>(cs.A, d);
 }
 
-constexpr int kEmMaxWaves = kEmMaxThreads / 64;
 // recomputed-density buckets re-sum every particle's density terms exactly
 // every kResumSweeps sweeps (and after a sweep with an annihilation); in the
 // other sweeps the running sums close the sweep
@@ -487,9 +486,10 @@ __device__ __forceinline__ double sqrt_det(const double* C)
 // threads compute the identical M-step, so a wave can publish an update to
 // its copy without waiting for the others.  The only workgroup barrier per
 // component update is the one inside the cross-wave reduction.
-template <int D, int KMAX, int P, bool STORE_E, typename R>
-__global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
+template <int D, int KMAX, int P, bool STORE_E, typename R, bool LEAN>
+__global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(CompressArgs A_in)
 {
+    constexpr int MAXW = em_max_waves(LEAN);
     constexpr int NT = ntri(D);
     constexpr int NS = 1 + D + NT;
     const int nthreads = blockDim.x;
@@ -499,15 +499,15 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
     const double halfT = 0.5 * T;
 
     __shared__ CompressArgs A;   // arguments read where they are used, not pinned in SGPRs
-    __shared__ CompState<R, D> compw[kEmMaxWaves][KMAX];
+    __shared__ CompState<R, D> compw[MAXW][KMAX];
     __shared__ CompState<R, D> bestc[KMAX];  // best state of the outer search over K
     __shared__ double red_d[2 * kMaxWaves * 2];
-    __shared__ R red_r[2 * kEmMaxWaves * NS];  // zero where no wave writes (em_block_sum)
+    __shared__ R red_r[2 * MAXW * NS];  // zero where no wave writes (em_block_sum)
     __shared__ int s_idx;
     __shared__ int s_flag;
 
     if (tid == 0) A = A_in;
-    for (int t = tid; t < 2 * kEmMaxWaves * NS; t += blockDim.x) red_r[t] = R(0);
+    for (int t = tid; t < 2 * MAXW * NS; t += blockDim.x) red_r[t] = R(0);
     __syncthreads();
     const int nwaves = A.nwaves;
     const int bucket = A.bucket;
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                                 accumulate(p, eold[p], Sden[p]);
                             }
                         }
-                        em_block_sum<NS, kEmMaxWaves>(sums, red_r, par_r, nwaves);
+                        em_block_sum<NS, MAXW>(sums, red_r, par_r, nwaves);
                         const R Nk = sums[0];
                         const R NkT = Nk - (R)halfT;
                         if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
@@ -913,7 +913,7 @@ __global__ __launch_bounds__(kEmMaxThreads) void k_em(CompressArgs A_in)
                             Sden[p] = R(1);
                         }
                     }
-                    block_sum<2, kEmMaxWaves>(lsum, red_d, par_d, nwaves);
+                    block_sum<2, MAXW>(lsum, red_d, par_d, nwaves);
                     // normalise the weights in this wave's copy: u_j /= G, c2_j -= log2 G
                     if (lane < Kslots && ((alive >> lane) & 1u)) {
                         comp[lane].u = comp[lane].u * m_rcp(G);
@@ -1299,26 +1299,49 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
 // host-side launch helpers, instantiated per (D, precision) translation unit
 // ===========================================================================
 template <int D, int KMAX, typename R, typename F>
-inline bool with_variant_kernel(int per_thread, bool store_e, F&& f)
+inline bool with_variant_kernel(int per_thread, int mode, F&& f)
 {
+    const bool store_e = (mode & kModeStoreE) != 0;
+    if (mode & kModeLean) {
+        // lean builds (at most 128 VGPRs): FP32 iterations only
+        if constexpr (std::is_same<R, float>::value) {
+            if (store_e && per_thread == 1) {
+                f(k_em<D, KMAX, 1, true, R, true>);
+                return true;
+            }
+            if (store_e && per_thread == 2) {
+                f(k_em<D, KMAX, 2, true, R, true>);
+                return true;
+            }
+            if (!store_e && per_thread == 4) {
+                f(k_em<D, KMAX, 4, false, R, true>);
+                return true;
+            }
+            if (!store_e && per_thread == 8) {
+                f(k_em<D, KMAX, 8, false, R, true>);
+                return true;
+            }
+        }
+        return false;
+    }
     if (!store_e) {
         if (per_thread == 8) {
-            f(k_em<D, KMAX, 8, false, R>);
+            f(k_em<D, KMAX, 8, false, R, false>);
             return true;
         }
         if (per_thread == 16) {
-            f(k_em<D, KMAX, 16, false, R>);
+            f(k_em<D, KMAX, 16, false, R, false>);
             return true;
         }
         return false;
     }
     switch (per_thread) {
-        case 1: f(k_em<D, KMAX, 1, true, R>); return true;
-        case 2: f(k_em<D, KMAX, 2, true, R>); return true;
-        case 4: f(k_em<D, KMAX, 4, true, R>); return true;
+        case 1: f(k_em<D, KMAX, 1, true, R, false>); return true;
+        case 2: f(k_em<D, KMAX, 2, true, R, false>); return true;
+        case 4: f(k_em<D, KMAX, 4, true, R, false>); return true;
         case 8:
             if constexpr (KMAX == 8) {
-                f(k_em<D, KMAX, 8, true, R>);
+                f(k_em<D, KMAX, 8, true, R, false>);
                 return true;
             }
             return false;
@@ -1327,29 +1350,32 @@ inline bool with_variant_kernel(int per_thread, bool store_e, F&& f)
 }
 
 template <int D, typename R>
-int launch_bucket_dr(int kmax_tpl, int per_thread, bool store_e, int waves, const CompressArgs& a, int grid,
+int launch_bucket_dr(int kmax_tpl, int per_thread, int mode, int waves, const CompressArgs& a, int grid,
                      hipStream_t st)
 {
-    if (waves < 1 || waves > kEmMaxWaves || a.nwaves != waves) return -1;
+    if (waves < 1 || waves > em_max_waves((mode & kModeLean) != 0) || a.nwaves != waves) return -1;
     const dim3 g(grid), b(64 * waves);
     bool ok = false;
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, a); };
     if (kmax_tpl == 8)
-        ok = with_variant_kernel<D, 8, R>(per_thread, store_e, go);
+        ok = with_variant_kernel<D, 8, R>(per_thread, mode, go);
     else if (kmax_tpl == 16)
-        ok = with_variant_kernel<D, 16, R>(per_thread, store_e, go);
+        ok = with_variant_kernel<D, 16, R>(per_thread, mode, go);
     if (!ok) return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// persistent grid: resident workgroups per CU times the CU count (cached)
+// persistent grid: resident workgroups per CU times the CU count (cached);
+// 0 for a variant that is not built
 template <int D, typename R>
-int grid_dr(int kmax_tpl, int per_thread, bool store_e, int waves)
+int grid_dr(int kmax_tpl, int per_thread, int mode, int waves)
 {
-    static int cache[2][17][2][kEmMaxWaves + 1] = {};
-    if (per_thread < 1 || per_thread > 16 || waves < 1 || waves > kEmMaxWaves) return 0;
+    static int cache[2][17][4][kEmMaxWaves + 1] = {};
+    if (per_thread < 1 || per_thread > 16 || mode < 0 || mode > 3 || waves < 1 ||
+        waves > em_max_waves((mode & kModeLean) != 0))
+        return 0;
     const int ki = kmax_tpl == 8 ? 0 : 1;
-    int& slot = cache[ki][per_thread][store_e ? 1 : 0][waves];
+    int& slot = cache[ki][per_thread][mode][waves];
     if (slot > 0) return slot;
     int dev = 0, ncu = 0, nb = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -1362,9 +1388,9 @@ int grid_dr(int kmax_tpl, int per_thread, bool store_e, int waves)
     };
     bool ok = false;
     if (kmax_tpl == 8)
-        ok = with_variant_kernel<D, 8, R>(per_thread, store_e, q);
+        ok = with_variant_kernel<D, 8, R>(per_thread, mode, q);
     else
-        ok = with_variant_kernel<D, 16, R>(per_thread, store_e, q);
+        ok = with_variant_kernel<D, 16, R>(per_thread, mode, q);
     if (!ok) return 0;
     if (nb < 1) nb = 1;
     slot = nb * ncu;

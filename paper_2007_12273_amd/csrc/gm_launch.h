@@ -46,18 +46,37 @@ __host__ __device__ constexpr const Bucket& bucket_cfg(int kmax_tpl, int b)
 constexpr int kMaxCellParticles = 8192;
 
 // Launch variants a bucket can run with (the autotuner picks among them):
-// particles per thread and whether the density terms stay in registers.
-// A variant fits a bucket when 64 * waves * per_thread >= max_n with
-// waves = ceil(max_n / (64 * per_thread)) <= kEmMaxThreads / 64.
+// particles per thread, whether the density terms stay in registers, and
+// the build: standard (workgroups of up to 512 threads, up to 256 VGPRs per
+// lane, two waves per SIMD) or lean (up to 1024 threads, at most 128 VGPRs,
+// so twice the waves per SIMD: more cells in flight per CU, and 16-wave
+// workgroups for the largest cells).  Lean builds exist for FP32 iterations
+// only.  A variant fits a bucket when 64 * waves * per_thread >= max_n with
+// waves = ceil(max_n / (64 * per_thread)) <= the build's waves.
 // Register-resident densities with 8 particles per thread are built for
 // kmax 8 only (16 slots x 8 particles do not fit the register file).
+// Launch mode bits: kModeStoreE (densities in registers), kModeLean.
+constexpr int kModeStoreE = 1;
+constexpr int kModeLean = 2;
 struct EmVariant {
     int per_thread;
     bool store_e;
+    bool lean;
 };
-constexpr int kNumVariants = 6;
-constexpr EmVariant kVariants[kNumVariants] = {{1, true}, {2, true}, {4, true}, {8, true}, {8, false}, {16, false}};
+constexpr int kNumVariants = 10;
+constexpr EmVariant kVariants[kNumVariants] = {{1, true, false}, {2, true, false}, {4, true, false},
+                                              {8, true, false}, {8, false, false}, {16, false, false},
+                                              {1, true, true},  {2, true, true},  {4, false, true},
+                                              {8, false, true}};
 constexpr int kEmMaxThreads = 512;
+constexpr int kEmLeanThreads = 1024;
+__host__ __device__ constexpr int em_max_waves(bool lean) { return (lean ? kEmLeanThreads : kEmMaxThreads) / 64; }
+constexpr int kEmMaxWaves = kEmLeanThreads / 64;
+// launch-plan code of a variant: per_thread * 1000 + waves * 10 + mode
+__host__ __device__ constexpr int em_variant_code(int per_thread, int waves, int mode)
+{
+    return per_thread * 1000 + waves * 10 + mode;
+}
 
 // ---- reconstruct ---------------------------------------------------------
 struct ReconArgs {

@@ -1,7 +1,7 @@
 // gm_std.hip -- standard (non-adaptive) EM-GM with K-means start and Anderson
 // acceleration (Sec. 3.4), FP32 E/M iterations, FP64 parameter mixing.
 //
-// One wave per cell (a 64-thread workgroup), grid over the cells; only
+// One 256-thread workgroup (four waves) per cell, grid over the cells; only
 // cells that k_moments marked for EM are fitted, k_finish then applies the
 // unpenalised joint step (the standard EM step that follows the iteration)
 // and handles every other cell.

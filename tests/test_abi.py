@@ -89,3 +89,35 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.gm_compress_standard(*args(4, 0, 6)) == -1    # memory above 5
     o.estep_fp64 = 1
     assert lib.gm_compress_standard(*args(4, 0, 3)) == -4    # FP64 iterations not built
+
+
+def test_launch_plan_codes_checked_on_host():
+    """gm_autotune_set rejects a variant code that is not built or does not
+    cover its bucket before it touches a device."""
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    maxn16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
+
+    def codes(P, mode, maxw):
+        return [P * 1000 + min(maxw, -(-m // (64 * P))) * 10 + mode for m in maxn16]
+
+    def setp(c, fp64=0):
+        return lib.gm_autotune_set(3, 16, fp64, 0, (ctypes.c_int32 * 12)(*c), None)
+
+    base = codes(16, 0, 8)
+    for bad in (2 * 1000 + 10 + 4,      # mode 4 unknown
+                3 * 1000 + 10 + 1,      # 3 particles per thread not built
+                8 * 1000 + 10 + 1,      # register-resident 8 per thread only at kmax 8
+                1 * 1000 + 90 + 1,      # 9 waves: above the standard build's 8
+                1 * 1000 + 170 + 3,     # 17 waves: above the lean build's 16
+                4 * 1000 + 10 + 3):     # lean register-resident 4 per thread not built
+        c = list(base)
+        c[0] = bad
+        assert setp(c) == -1, bad
+    c = list(base)
+    c[9] = 2 * 1000 + 15 * 10 + 3  # 1920 < 2048 particles: does not cover the bucket
+    assert setp(c) == -1
+    c[9] = 2 * 1000 + 16 * 10 + 3
+    assert setp(c, fp64=1) == -1   # lean builds are FP32 only

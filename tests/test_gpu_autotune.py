@@ -15,20 +15,22 @@ pytestmark = pytest.mark.gpu
 
 MAXN16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
 MAXN8 = [64, 128, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 8192]
-VARIANTS = [(1, True), (2, True), (4, True), (8, True), (8, False), (16, False)]
+# (particles per thread, register-resident densities, lean build)
+VARIANTS = [(1, True, False), (2, True, False), (4, True, False), (8, True, False), (8, False, False),
+            (16, False, False), (1, True, True), (2, True, True), (4, False, True), (8, False, True)]
 
 
 def _codes(kmax, variant):
-    P, se = variant
+    P, se, lean = variant
     if se and P == 8 and kmax > 8:
         return None
     out = []
     for m in (MAXN8 if kmax <= 8 else MAXN16):
         w = -(-m // (64 * P))
-        if w > 8:
+        if w > (16 if lean else 8):
             out.append(None)
         else:
-            out.append(P * 100 + w * 10 + (1 if se else 0))
+            out.append(P * 1000 + w * 10 + (1 if se else 0) + (2 if lean else 0))
     return out
 
 
@@ -54,7 +56,7 @@ def test_every_variant_matches_oracle_replay(kmax):
                 continue
             # buckets the variant cannot cover run recomputed densities with
             # 16 particles per thread
-            fill = [c if c is not None else 1600 + 10 * (-(-default[b] // 1024)) for b, c in enumerate(codes)]
+            fill = [c if c is not None else 16000 + 10 * (-(-default[b] // 1024)) for b, c in enumerate(codes)]
             api.autotune_set(3, kmax, fill)
             g = host(api.compress(v, a, off, kmax, seed=9, fixed_sweeps=fs, max_sweeps=20))
             assert np.array_equal(g["sweeps"], o["sweeps"])
@@ -76,7 +78,7 @@ def test_autotune_installs_a_working_plan():
         print("autotune:", rep)
         assert rep["builtin_em_ms"] > 0 and rep["tuned_em_ms"] > 0
         for code, lane in zip(rep["variant"], rep["lane"]):
-            assert code // 100 in (1, 2, 4, 8, 16) and 0 <= lane <= 3
+            assert code // 1000 in (1, 2, 4, 8, 16) and code % 10 <= 3 and 0 <= lane <= 3
         tuned = host(comp.out.as_dict())
         again = host(comp(v, a, offg).as_dict())
         for k in ("K", "sweeps", "status"):
