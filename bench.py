@@ -99,6 +99,8 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="keep the built-in EM launch plans (no gm_autotune)")
     p.add_argument("--no-pool", action="store_true",
                    help="generate the training cells in this process (no child processes; for profiler runs)")
+    p.add_argument("--visits-out", default=None,
+                   help="write per-cell particle counts and component updates of the cold (and warm) fit to this .npz")
     p.add_argument("--copy-check", action="store_true",
                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters in profiles)")
     return p.parse_args()
@@ -464,6 +466,8 @@ def main():
     else:
         ms, em_ms, visits, phases, Kout, wr = ms_cold, ph_cold["em"], cold["visits"], ph_cold, cold["K"], cold
 
+    if args.visits_out:
+        np.savez(args.visits_out, n=counts, visits_cold=cold["visits"], visits_warm=wr["visits"])
     em_flops = float((counts * visits).sum()) * FLOPS_PER_UPDATE[D]
     tr = EM_TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if (warm and tr and tr["sources_sha256"] == em_sources_digest()) else None

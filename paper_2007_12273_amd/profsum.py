@@ -2,6 +2,7 @@
 
     python -m paper_2007_12273_amd.profsum trace  <kernel_trace.csv>
     python -m paper_2007_12273_amd.profsum bytes  <FETCH counter csv> <WRITE counter csv>
+    python -m paper_2007_12273_amd.profsum insts  <visits.npz> <call>:<cold|warm> <counter csv> [...]
 
 trace: per-kernel dispatch counts and durations, and per gm_compress call
 (a call starts with the k_plan_reset dispatch) the span of its EM phase,
@@ -12,6 +13,15 @@ EM roofline is quoted on).
 bytes: per gm_compress call the FETCH_SIZE and WRITE_SIZE counter totals
 (KiB) over its k_em dispatches, and the same counters for the largest
 device copy in the run (a plain copy of known size calibrates them).
+
+insts: instruction counters (any SQ_ counters, one or more csv files of
+runs with the same launch sequence) of the k_em dispatches of one
+gm_compress call, per wave-update: a component update executed by one
+wave of the cell's workgroup.  A dispatch's cells are those of its length
+bucket, which under the built-in launch plan holds the cells of up to
+64 * per_thread * waves particles (above the next smaller bucket's bound);
+visits.npz (bench.py --visits-out) gives the per-cell counts and updates of
+the cold and the warm fit.
 """
 from __future__ import annotations
 
@@ -28,10 +38,13 @@ def _rows(path):
 def _calls(rows, key_start):
     """Split dispatches (in dispatch order) into gm_compress calls."""
     rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
-    calls, cur = [], None
+    calls, cur, last = [], None, None
     for r in rows:
         name = r["Kernel_Name"]
-        if "k_plan_reset" in name:
+        # counter files hold one row per (dispatch, counter)
+        first = r["Dispatch_Id"] != last
+        last = r["Dispatch_Id"]
+        if "k_plan_reset" in name and first:
             cur = []
             calls.append(cur)
         if cur is not None and "k_em<" in name:
@@ -82,11 +95,47 @@ def bytes_(fetch_path, write_path):
         print("  call %2d: FETCH_SIZE %12.0f  WRITE_SIZE %12.0f" % (i, f, w))
 
 
+def _dispatch_shape(r):
+    """(particles per thread, waves) of a k_em dispatch row."""
+    args = r["Kernel_Name"].split("k_em<", 1)[1].split(">", 1)[0].split(",")
+    return int(args[2]), int(r["Workgroup_Size"]) // 64
+
+
+def insts(visits_path, spec, paths):
+    import numpy as np
+    z = np.load(visits_path)
+    n = z["n"]
+    call, which = spec.split(":")
+    visits = z["visits_" + which]
+    tot, wave_updates, updates = OrderedDict(), 0, 0
+    for path in paths:
+        disp = OrderedDict()
+        for r in _calls(_rows(path), "k_plan_reset")[int(call)]:
+            d = disp.setdefault(r["Dispatch_Id"], {"row": r, "c": {}})
+            d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        shapes = sorted({(64 * P * W, W) for P, W in (_dispatch_shape(d["row"]) for d in disp.values())})
+        wu, up, lo = 0, 0, 0
+        for hi, W in shapes:
+            sel = (n > lo) & (n <= hi)
+            up += int(visits[sel].sum())
+            wu += int(visits[sel].sum()) * W
+            lo = hi
+        wave_updates, updates = wu, up
+        for d in disp.values():
+            for k, v in d["c"].items():
+                tot[k] = tot.get(k, 0.0) + v
+    print("call %s (%s fit): %d component updates, %d wave-updates" % (call, which, updates, wave_updates))
+    for k, v in tot.items():
+        print("  %-32s %14.4g total %10.2f per wave-update" % (k, v, v / max(1, wave_updates)))
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "trace":
         trace(argv[1])
     elif len(argv) >= 3 and argv[0] == "bytes":
         bytes_(argv[1], argv[2])
+    elif len(argv) >= 4 and argv[0] == "insts":
+        insts(argv[1], argv[2], argv[3:])
     else:
         print(__doc__)
         return 2
