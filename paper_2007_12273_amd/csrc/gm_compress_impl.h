@@ -425,9 +425,9 @@ __device__ __forceinline__ void em_block_sum(T (&x)[NV], T* buf, int& parity, in
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x140>(x[v]);  // row_mirror
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142, 0xa>(x[v]);  // row_bcast:15
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142>(x[v]);  // row_bcast:15
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143, 0xc>(x[v]);  // row_bcast:31
+    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143>(x[v]);  // row_bcast:31
     if (nwaves == 1) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);

@@ -56,7 +56,11 @@ __device__ __forceinline__ double unit53(uint64_t x) { return (double)(x >> 11) 
 
 // ---------------------------------------------------------------------------
 // 64-lane sums with DPP: quad swaps, half-row and row mirrors give every lane
-// its 16-lane row total; two row broadcasts fold rows into lane 63.
+// its 16-lane row total; two row broadcasts (lane 15 of each row into the
+// next row, lane 31 into rows 2 and 3) fold the rows into lane 63, which
+// ends with (R3 + R2) + (R1 + R0).  Only lane 63's value is used, so the
+// broadcasts write every row (a lane without a source row adds zero): with
+// full row masks the move fuses into the add, one instruction per level.
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ int dpp_i(int x)
@@ -70,8 +74,8 @@ __device__ __forceinline__ float wave_sum(float x)
     x += __int_as_float(dpp_i<0x4E>(__float_as_int(x)));       // quad_perm [2,3,0,1]
     x += __int_as_float(dpp_i<0x141>(__float_as_int(x)));      // row_half_mirror
     x += __int_as_float(dpp_i<0x140>(__float_as_int(x)));      // row_mirror
-    x += __int_as_float(dpp_i<0x142, 0xa>(__float_as_int(x))); // row_bcast:15
-    x += __int_as_float(dpp_i<0x143, 0xc>(__float_as_int(x))); // row_bcast:31
+    x += __int_as_float(dpp_i<0x142>(__float_as_int(x))); // row_bcast:15
+    x += __int_as_float(dpp_i<0x143>(__float_as_int(x))); // row_bcast:31
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
@@ -90,8 +94,8 @@ __device__ __forceinline__ double wave_sum(double x)
     x += dpp_d<0x4E>(x);
     x += dpp_d<0x141>(x);
     x += dpp_d<0x140>(x);
-    x += dpp_d<0x142, 0xa>(x);
-    x += dpp_d<0x143, 0xc>(x);
+    x += dpp_d<0x142>(x);
+    x += dpp_d<0x143>(x);
     const int64_t b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
     const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);

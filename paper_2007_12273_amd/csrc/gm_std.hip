@@ -308,9 +308,9 @@ __global__ __launch_bounds__(kStdThreads) void k_std(StdArgs P)
 #pragma unroll
         for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x140>(sums[t]);
 #pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x142, 0xa>(sums[t]);
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x142>(sums[t]);
 #pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x143, 0xc>(sums[t]);
+        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x143>(sums[t]);
         if (lane == 63)
 #pragma unroll
             for (int t = 0; t < KMAX * NS; ++t) red_f[wid][t] = sums[t];
