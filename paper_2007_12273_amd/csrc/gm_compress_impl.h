@@ -394,6 +394,9 @@ __device__ __forceinline__ R log2_term(const CompState<R, D>& cs, const R (&x)[D
 // every kResumSweeps sweeps (and after a sweep with an annihilation); in the
 // other sweeps the running sums close the sweep
 constexpr int kResumSweeps = 4;
+// largest finite value of the iteration precision
+template <typename R>
+constexpr double kBigFinite = std::is_same<R, float>::value ? 3.4028234663852886e38 : 1.7976931348623157e308;
 
 template <int CTRL, int ROW_MASK = 0xf, typename T>
 __device__ __forceinline__ T dpp_get(T x)
@@ -706,14 +709,15 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                 // flagged in `big` got a term more than 2^64 above their reference
                 // (a component moved onto a particle that had been rebased far
                 // down): rebase them.  The branch is wave-uniform and rarely taken.
-                auto repair_store = [&](uint32_t low, uint32_t big) {
+                // The flags are per-particle lane masks (SALU), not VGPR bit sets.
+                auto repair_store = [&](bool any, const bool (&low)[P], const bool (&big)[P]) {
                     if constexpr (STORE_E) {
-                        if (__builtin_amdgcn_ballot_w64((low | big) != 0) == 0) return;
+                        if (__builtin_amdgcn_ballot_w64(any) == 0) return;
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            if ((big >> p) & 1u) {
+                            if (big[p]) {
                                 Sden[p] = rebase_store(e[p], x[p], ref[p]);
-                            } else if ((low >> p) & 1u) {
+                            } else if (low[p]) {
                                 Sden[p] = resum(e[p]);
                                 if (!(Sden[p] > rebase_below)) Sden[p] = rebase_store(e[p], x[p], ref[p]);
                             }
@@ -738,7 +742,10 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                         for (int t = 0; t < NS; ++t) sums[t] = R(0);
                         [[maybe_unused]] R eold[STORE_E ? 1 : P];
                         auto accumulate = [&](int p, R ek, R den) {
-                            const R inv = den > R(0) ? fast_rcp(den) : R(0);
+                            // den > 0 for every particle of a fitted cell (the rebase keeps
+                            // it above 2^-40); the clamp keeps a zero from turning a
+                            // zero-weight padding particle's 0 * inf into NaN
+                            const R inv = fmin(fast_rcp(den), R(kBigFinite<R>));
                             const R g = a[p] * ek * inv;
                             R d[D];
 #pragma unroll
@@ -774,16 +781,18 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                             --K;
                             annihilated = true;
                             if constexpr (STORE_E) {
-                                uint32_t low = 0;
+                                bool low[P], big[P], any = false;
 #pragma unroll
                                 for (int p = 0; p < P; ++p) {
                                     const R s_old = Sden[p];
                                     const R s_new = s_old - e[p][k];
                                     e[p][k] = R(0);
                                     Sden[p] = s_new;
-                                    low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
+                                    low[p] = !(s_new > R(1e-3) * s_old);
+                                    big[p] = false;
+                                    any |= low[p];
                                 }
-                                repair_store(low, 0u);
+                                repair_store(any, low, big);
                             } else {
 #pragma unroll
                                 for (int p = 0; p < P; ++p) {
@@ -825,7 +834,7 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                         if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
                         if (lane == 0) comp[k] = cn;  // this wave's copy; read back only by this wave
                         if constexpr (STORE_E) {
-                            uint32_t low = 0, big = 0;
+                            bool low[P], big[P], any = false;
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
                                 const R dt = log2_term<R, D>(cn, x[p]) - ref[p];
@@ -834,10 +843,11 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                                 const R s_new = s_old - e[p][k] + enew;
                                 e[p][k] = enew;
                                 Sden[p] = s_new;
-                                low |= (uint32_t)!(s_new > R(1e-3) * s_old) << p;
-                                big |= (uint32_t)(dt > R(64)) << p;
+                                low[p] = !(s_new > R(1e-3) * s_old);
+                                big[p] = dt > R(64);
+                                any |= low[p] | big[p];
                             }
-                            repair_store(low, big);
+                            repair_store(any, low, big);
                         } else {
 #pragma unroll
                             for (int p = 0; p < P; ++p) {
