@@ -407,48 +407,107 @@ __device__ __forceinline__ T dpp_get(T x)
         return dpp_d<CTRL, ROW_MASK>(x);
 }
 
+// Wave sums of NV FP32 values, transposed: values are paired so that each
+// step halves the registers still to be reduced.  A lane-half swap
+// (v_permlane32_swap) of x[2i] and x[2i+1] plus one add leaves x[2i]'s sums
+// over lane pairs (l, l + 32) in lanes 0-31 and x[2i+1]'s in lanes 32-63; a
+// row swap (v_permlane16_swap) of two such registers plus one add leaves
+// four values' 4-lane partial sums, one per 16-lane row; four in-row DPP
+// levels then give every lane its row's total.  Value v ends in register
+// v / 4, in row tv_row(v): about 28 VALU instructions for ten values
+// against 60 for ten separate 64-lane trees.
+// An unpaired last value is swapped with itself (both halves, or both rows,
+// then hold it).
+constexpr int tv_row(int v) { return 2 * (v & 1) + ((v >> 1) & 1); }
+
+template <int NV>
+__device__ __forceinline__ void wave_sums_transposed(const float (&x)[NV], float (&b)[(NV + 3) / 4])
+{
+    constexpr int NA = (NV + 1) / 2, NB = (NV + 3) / 4;
+    float a[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const unsigned lo = __float_as_uint(x[2 * i]);
+        const unsigned hi = __float_as_uint(x[2 * i + 1 < NV ? 2 * i + 1 : 2 * i]);
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const unsigned f = __float_as_uint(a[2 * j]);
+        const unsigned g = __float_as_uint(a[2 * j + 1 < NA ? 2 * j + 1 : 2 * j]);
+        const auto r = __builtin_amdgcn_permlane16_swap(f, g, false, false);
+        b[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] += dpp_get<0xB1>(b[j]);   // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] += dpp_get<0x4E>(b[j]);   // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] += dpp_get<0x141>(b[j]);  // row_half_mirror
+#pragma unroll
+    for (int j = 0; j < NB; ++j) b[j] += dpp_get<0x140>(b[j]);  // row_mirror
+}
+
 // Workgroup sum of the NV M-step sums of one component update, delivered to
-// every thread.  The 64-lane tree of wave_sum is applied to all NV values one
-// level at a time, so the independent DPP operations fill each other's wait
-// states.  Lane 63 of every wave, where the tree ends, publishes its wave's
-// sums; after one barrier
-// lane v < NV adds value v over all MAXW slots in wave order: slots of absent
-// waves hold zeros (the buffer is cleared when the kernel starts and only
-// present waves write), so no per-wave test is needed.  The additions happen
-// in the same order as in block_sum.
+// every thread.  FP32: the transposed wave sums above; lane 15 of each row
+// publishes the values its row holds.  FP64: the 64-lane tree of wave_sum
+// applied to all NV values one level at a time (the independent DPP
+// operations fill each other's wait states); lane 63, where the tree ends,
+// publishes.  After one barrier lane v < NV adds value v over all MAXW
+// slots in wave order: slots of absent waves hold zeros (the buffer is
+// cleared when the kernel starts and only present waves write), so no
+// per-wave test is needed.
 template <int NVMAX, int MAXW, typename T, int NV>
 __device__ __forceinline__ void em_block_sum(T (&x)[NV], T* buf, int& parity, int nwaves)
 {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0xB1>(x[v]);   // quad_perm [1,0,3,2]
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x4E>(x[v]);   // quad_perm [2,3,0,1]
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x141>(x[v]);  // row_half_mirror
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x140>(x[v]);  // row_mirror
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142>(x[v]);  // row_bcast:15
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143>(x[v]);  // row_bcast:31
-    if (nwaves == 1) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);
-        return;
-    }
-    // lane 63 holds the wave's sums
-    T* b = buf + parity * (MAXW * NVMAX);
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 63) {
+    T* bb = buf + parity * (MAXW * NVMAX);
+    if constexpr (std::is_same<T, float>::value) {
+        constexpr int NB = (NV + 3) / 4;
+        float b[NB];
+        wave_sums_transposed<NV>(x, b);
+        if (nwaves == 1) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) b[wid * NVMAX + v] = x[v];
+            for (int v = 0; v < NV; ++v) x[v] = lane_bcast(b[v / 4], 16 * tv_row(v) + 15);
+            return;
+        }
+        if ((lane & 15) == 15) {
+            const int r = lane >> 4;
+            const int off = 2 * (r & 1) + (r >> 1);  // value index within each group of four
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (4 * j + off < NV) bb[wid * NVMAX + 4 * j + off] = b[j];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0xB1>(x[v]);   // quad_perm [1,0,3,2]
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x4E>(x[v]);   // quad_perm [2,3,0,1]
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x141>(x[v]);  // row_half_mirror
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x140>(x[v]);  // row_mirror
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x142>(x[v]);  // row_bcast:15
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] += dpp_get<0x143>(x[v]);  // row_bcast:31
+        if (nwaves == 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) x[v] = lane_bcast(x[v], 63);
+            return;
+        }
+        if (lane == 63) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) bb[wid * NVMAX + v] = x[v];
+        }
     }
     __syncthreads();
     T t = T(0);
     if (lane < NV) {
         T part[MAXW];
 #pragma unroll
-        for (int w = 0; w < MAXW; ++w) part[w] = b[w * NVMAX + lane];
+        for (int w = 0; w < MAXW; ++w) part[w] = bb[w * NVMAX + lane];
         t = part[0];
 #pragma unroll
         for (int w = 1; w < MAXW; ++w) t += part[w];

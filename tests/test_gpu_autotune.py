@@ -60,7 +60,8 @@ def test_every_variant_matches_oracle_replay(kmax):
             api.autotune_set(3, kmax, fill)
             g = host(api.compress(v, a, off, kmax, seed=9, fixed_sweeps=fs, max_sweeps=20))
             assert np.array_equal(g["sweeps"], o["sweeps"])
-            _check_record(g, o, 3, k_frac=0.9, par_frac=0.85, par_max=1e-2, label="variant %s kmax %d" % (var, kmax))
+            _check_record(g, o, 3, k_frac=0.9, par_frac=0.85, par_max=1e-2, label="variant %s kmax %d" % (var, kmax),
+                          n=np.diff(d["cell_off"]))
     finally:
         api.autotune_reset()
 
@@ -86,6 +87,7 @@ def test_autotune_installs_a_working_plan():
         o = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=16, seed=2003, max_sweeps=60)
         fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
         g = host(comp(v, a, offg, fixed_sweeps=fs).as_dict())
-        _check_record(g, o, 3, k_frac=0.95, par_frac=0.9, par_max=1e-2, label="tuned plan replay")
+        _check_record(g, o, 3, k_frac=0.95, par_frac=0.9, par_max=1e-2, label="tuned plan replay",
+                      n=np.diff(sub["cell_off"]))
     finally:
         api.autotune_reset()

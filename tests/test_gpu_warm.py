@@ -253,7 +253,7 @@ def test_pipeline_warm_compress_matches_oracle():
     g2 = host(api.compress(v, a, off, 16, seed=4, max_sweeps=150, init=gi, fixed_sweeps=fs))
     np.testing.assert_array_equal(g2["sweeps"], o2["sweeps"])
     _check_record(g2, o2, 3, cells=list(np.nonzero(keep)[0]), k_frac=0.95, par_frac=0.9, par_max=1e-2,
-                  label="pipeline replay")
+                  label="pipeline replay", n=np.diff(d["cell_off"]))
     m.close()
 
 
@@ -265,7 +265,7 @@ def test_warm_fallback_matches_oracle():
     assert ((o["status"] & FALLBACK) != 0).all()
     np.testing.assert_array_equal(g["status"] & FALLBACK, o["status"] & FALLBACK)
     np.testing.assert_array_equal(g["sweeps"], o["sweeps"])
-    _check_record(g, o, 3, k_frac=0.9, par_frac=0.9, par_max=2e-3, label="fallback")
+    _check_record(g, o, 3, k_frac=0.9, par_frac=0.9, par_max=2e-3, label="fallback", n=np.diff(d["cell_off"]))
     # a start at the generating Gaussian is kept
     iu = np.triu_indices(3)
     good = {"K": np.ones(12, np.int32), "omega": np.zeros((12, 16)), "mu": np.zeros((12, 16, 3)),
