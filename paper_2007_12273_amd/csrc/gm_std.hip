@@ -297,23 +297,21 @@ __global__ __launch_bounds__(kStdThreads) void k_std(StdArgs P)
                 }
             }
         }
-        // wave sums (the DPP tree of em_block_sum, every value level by level;
-        // lane 63 ends with the totals), then the waves' partials in wave order
+        // wave sums (the transposed reduction of the adaptive path: value v
+        // ends in register v / 4, row tv_row(v); lane 15 of each row
+        // publishes its row's values), then the waves' partials in wave order
+        {
+            constexpr int NV = KMAX * NS, NB = (NV + 3) / 4;
+            float b[NB];
+            wave_sums_transposed<NV>(sums, b);
+            if ((lane & 15) == 15) {
+                const int r = lane >> 4;
+                const int off = 2 * (r & 1) + (r >> 1);
 #pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0xB1>(sums[t]);
-#pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x4E>(sums[t]);
-#pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x141>(sums[t]);
-#pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x140>(sums[t]);
-#pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x142>(sums[t]);
-#pragma unroll
-        for (int t = 0; t < KMAX * NS; ++t) sums[t] += dpp_get<0x143>(sums[t]);
-        if (lane == 63)
-#pragma unroll
-            for (int t = 0; t < KMAX * NS; ++t) red_f[wid][t] = sums[t];
+                for (int q = 0; q < NB; ++q)
+                    if (4 * q + off < NV) red_f[wid][4 * q + off] = b[q];
+            }
+        }
         block_sum<NKM, kStdWaves>(lsum, red_d, par, kStdWaves);
         for (int t = tid; t < KMAX * NS; t += kStdThreads) {
             float v = red_f[0][t];
