@@ -593,8 +593,7 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
         const R sdc = (R)sdc64;
         const double lnc0 = -0.5 * D * kLnTwoPi - log(sdc64);
         const double lnN = log((double)n);
-        int K_den = -1;
-        R inv_den = R(0);
+        R inv_den = R(0);  // 1 / (N - T K / 2) of eq. omegak, set whenever K changes
         const int64_t o0 = A.off[c];
         const double* vc = A.v + o0 * D;
         const int kmax = A.kmax;
@@ -693,6 +692,7 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
             int K_best = 0, s_total = 0;
             R G_best = R(0);
             for (;;) {
+                inv_den = m_rcp((R)(N - halfT * K));
                 // ---------------- initial density terms ------------------------------
                 if constexpr (STORE_E) {
                     for (int j = 0; j < K; ++j) {
@@ -838,6 +838,7 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
                             alive &= ~(1u << k);
                             G -= cku;
                             --K;
+                            inv_den = m_rcp((R)(N - halfT * K));
                             annihilated = true;
                             if constexpr (STORE_E) {
                                 bool low[P], big[P], any = false;
@@ -882,10 +883,6 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(Co
 #pragma unroll
                             for (int j = i; j < D; ++j)
                                 cn.S[tri_idx<D>(i, j)] = sums[1 + D + tri_idx<D>(i, j)] * invN - dl[i] * dl[j];
-                        if (K != K_den) {  // 1 / (N - T K / 2), recomputed when K changes
-                            inv_den = m_rcp((R)(N - halfT * K));
-                            K_den = K;
-                        }
                         const R wk = NkT * inv_den;
                         const R unew = wk * G;
                         G = G - cku + unew;

@@ -34,17 +34,17 @@ def _codes(kmax, variant):
     return out
 
 
-def _batch():
+def _batch(D=3):
     sizes = [40, 64, 100, 128, 200, 256, 400, 512, 700, 768, 900, 1024, 1200, 1280, 1500, 1536, 1700, 1792, 1900,
              2048, 2500, 3000, 3584, 4096, 5000]
-    parts = [synth.random_cells(300 + i, 1, 3, n, n, k_lo=2, k_hi=4) for i, n in enumerate(sizes)]
+    parts = [synth.random_cells(300 + i, 1, D, n, n, k_lo=2, k_hi=4) for i, n in enumerate(sizes)]
     return synth.concat_cells(parts)
 
 
-@pytest.mark.parametrize("kmax", [8, 16])
-def test_every_variant_matches_oracle_replay(kmax):
+@pytest.mark.parametrize("D,kmax", [(3, 8), (3, 16), (1, 8), (1, 16)])
+def test_every_variant_matches_oracle_replay(D, kmax):
     from paper_2007_12273_amd import api
-    d = _batch()
+    d = _batch(D)
     v, a, off = to_gpu(d)
     o = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=kmax, seed=9, max_sweeps=20)
     fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
@@ -57,11 +57,11 @@ def test_every_variant_matches_oracle_replay(kmax):
             # buckets the variant cannot cover run recomputed densities with
             # 16 particles per thread
             fill = [c if c is not None else 16000 + 10 * (-(-default[b] // 1024)) for b, c in enumerate(codes)]
-            api.autotune_set(3, kmax, fill)
+            api.autotune_set(D, kmax, fill)
             g = host(api.compress(v, a, off, kmax, seed=9, fixed_sweeps=fs, max_sweeps=20))
             assert np.array_equal(g["sweeps"], o["sweeps"])
-            _check_record(g, o, 3, k_frac=0.9, par_frac=0.85, par_max=1e-2, label="variant %s kmax %d" % (var, kmax),
-                          n=np.diff(d["cell_off"]))
+            _check_record(g, o, D, k_frac=0.9, par_frac=0.85, par_max=1e-2,
+                          label="D %d variant %s kmax %d" % (D, var, kmax), n=np.diff(d["cell_off"]))
     finally:
         api.autotune_reset()
 
