@@ -52,6 +52,7 @@ extern "C" {
 #define GM_ENOMEM (-3)    /* workspace missing or smaller than required */
 #define GM_ENOTIMPL (-4)  /* combination not built into this library */
 #define GM_ENOCONV (-5)   /* iterative solve stopped above its tolerance */
+#define GM_EIO (-6)       /* a file could not be opened, read or written */
 
 /* ---- per-cell status bits ---- */
 #define GM_ST_SMALL_CELL_K1 (1 << 0)   /* n <= n_min: single Gaussian with the cell's moments */
@@ -322,6 +323,18 @@ void gm_warm_destroy(gm_warm* model);
  * floats (synchronous).  set_params also resets the Adam state. */
 int gm_warm_get_params(const gm_warm* model, float* host);
 int gm_warm_set_params(gm_warm* model, const float* host);
+/* Write the model's FP32 parameters to a file (synchronous): the 8 bytes
+ * "GMCRWRM1", int32 D, int32 kmax, uint64 gm_warm_param_count(), then the
+ * parameters in the get/set layout, host byte order.  The Adam state and
+ * step count are not stored.  GM_EIO if the file cannot be written. */
+int gm_warm_save(const gm_warm* model, const char* path);
+/* Create a model from a file written by gm_warm_save, with training buffers
+ * for batches of `batch` cells (as gm_warm_create; fresh Adam state).  The
+ * file is read and checked before any device memory is allocated: GM_EIO if
+ * it cannot be opened, is truncated or has trailing bytes, GM_EINVAL if it
+ * is not a model file of this layout (magic, D = 3, kmax 1..16, parameter
+ * count). */
+int gm_warm_load(gm_warm** model, const char* path, int32_t batch, void* stream);
 /* Copy the gradient of the last gm_warm_train_step to HOST memory
  * (synchronous; same layout as the parameters). */
 int gm_warm_gradients(const gm_warm* model, float* host);

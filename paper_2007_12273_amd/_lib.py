@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmcr.so")
 
-GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL, GM_ENOCONV = 0, -1, -2, -3, -4, -5
+GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL, GM_ENOCONV, GM_EIO = 0, -1, -2, -3, -4, -5, -6
 GM_TUNE_REPORT_LEN = 38
 
 STATUS = {
@@ -44,7 +44,7 @@ EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_autotu
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
-           "gm_warm_set_params", "gm_warm_gradients", "gm_warm_features", "gm_warm_forward_workspace",
+           "gm_warm_set_params", "gm_warm_gradients", "gm_warm_save", "gm_warm_load", "gm_warm_features", "gm_warm_forward_workspace",
            "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_profile_enable",
            "gm_profile_read", "gm_strerror", "gm_version")
 
@@ -108,6 +108,10 @@ def load():
     for name in ("gm_warm_get_params", "gm_warm_set_params", "gm_warm_gradients"):
         getattr(L, name).argtypes = [P, P]
         getattr(L, name).restype = ctypes.c_int
+    L.gm_warm_save.argtypes = [P, ctypes.c_char_p]
+    L.gm_warm_save.restype = ctypes.c_int
+    L.gm_warm_load.argtypes = [ctypes.POINTER(P), ctypes.c_char_p, I32, P]
+    L.gm_warm_load.restype = ctypes.c_int
     L.gm_warm_features.argtypes = [P, P, P, I64, I32, P, P, P]
     L.gm_warm_features.restype = ctypes.c_int
     L.gm_warm_forward_workspace.argtypes = [I64]

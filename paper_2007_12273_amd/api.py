@@ -7,6 +7,7 @@ allocates outputs, packs pointers and passes torch's current stream.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -381,14 +382,30 @@ def warm_decode(Y, frame, cell_off, kmax, out=None, stream=None):
 class WarmStart:
     """Handle of a gm_warm model (the perceptron and its training state)."""
 
-    def __init__(self, kmax, batch=1024, seed=0, device="cuda"):
+    def __init__(self, kmax, batch=1024, seed=0, device="cuda", path=None):
+        """A fresh model (seeded weights), or, with `path`, the model that
+        gm_warm_save wrote there (gm_warm_load; kmax is taken from the file)."""
         L = _lib.load()
-        self.kmax, self.batch, self.device = kmax, batch, torch.device(device)
+        self.batch, self.device = batch, torch.device(device)
         self.n_param = int(L.gm_warm_param_count())
         h = ctypes.c_void_p()
-        check(L.gm_warm_create(ctypes.byref(h), 3, kmax, batch, seed, _stream(None)), "gm_warm_create")
+        if path is None:
+            check(L.gm_warm_create(ctypes.byref(h), 3, kmax, batch, seed, _stream(None)), "gm_warm_create")
+            self.kmax = kmax
+        else:
+            check(L.gm_warm_load(ctypes.byref(h), os.fsencode(path), batch, _stream(None)), "gm_warm_load")
+            with open(path, "rb") as f:
+                self.kmax = int.from_bytes(f.read(16)[12:16], "little", signed=True)
         self._h = h
         self._ws = None
+
+    @classmethod
+    def load(cls, path, batch=1024, device="cuda"):
+        return cls(None, batch=batch, device=device, path=path)
+
+    def save(self, path):
+        """Write the parameters to `path` (gm_warm_save)."""
+        check(_lib.load().gm_warm_save(self._h, os.fsencode(path)), "gm_warm_save")
 
     def close(self):
         if self._h:

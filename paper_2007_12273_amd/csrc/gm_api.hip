@@ -690,6 +690,7 @@ const char* gm_strerror(int code)
         case GM_ENOMEM: return "workspace missing or too small";
         case GM_ENOTIMPL: return "not implemented in this build";
         case GM_ENOCONV: return "iterative solve did not reach its tolerance";
+        case GM_EIO: return "file could not be opened, read or written";
         default: return "unknown error";
     }
 }

@@ -22,8 +22,11 @@
 //   k_adam      Adam on FP32 master weights, refreshing the BF16 copies
 //   k_decode    network outputs -> initial mixtures (gm_init layout)
 //   k_targets   plain-EM mixtures -> training targets in the whitened frame
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <vector>
 
 #include "gm_device.h"
 
@@ -661,6 +664,56 @@ int gm_warm_set_params(gm_warm* m, const float* host)
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk), dim3(256), 0, 0, m->w, m->wb, (int64_t)NPARAM);
     if (launch_ok() != GM_OK) return GM_EHIP;
     return ok(hipDeviceSynchronize()) ? GM_OK : GM_EHIP;
+}
+
+// Model file: the 8 bytes "GMCRWRM1", int32 D, int32 kmax, uint64 parameter
+// count, then the FP32 parameters in the get/set layout (host byte order).
+static const char kWarmMagic[8] = {'G', 'M', 'C', 'R', 'W', 'R', 'M', '1'};
+
+int gm_warm_save(const gm_warm* m, const char* path)
+{
+    if (!m || !path) return GM_EINVAL;
+    std::vector<float> h(gm::NPARAM);
+    const int rc = gm_warm_get_params(m, h.data());
+    if (rc != GM_OK) return rc;
+    FILE* f = fopen(path, "wb");
+    if (!f) return GM_EIO;
+    const int32_t dk[2] = {m->D, m->kmax};
+    const uint64_t np = gm::NPARAM;
+    bool good = fwrite(kWarmMagic, 1, 8, f) == 8 && fwrite(dk, 4, 2, f) == 2 && fwrite(&np, 8, 1, f) == 1 &&
+                fwrite(h.data(), 4, h.size(), f) == h.size();
+    good = (fclose(f) == 0) && good;
+    return good ? GM_OK : GM_EIO;
+}
+
+int gm_warm_load(gm_warm** out, const char* path, int32_t batch, void* stream)
+{
+    if (!out || !path || batch < 1 || batch > (1 << 20)) return GM_EINVAL;
+    FILE* f = fopen(path, "rb");
+    if (!f) return GM_EIO;
+    char magic[8];
+    int32_t dk[2] = {0, 0};
+    uint64_t np = 0;
+    std::vector<float> h(gm::NPARAM);
+    int rc = GM_OK;
+    if (fread(magic, 1, 8, f) != 8 || fread(dk, 4, 2, f) != 2 || fread(&np, 8, 1, f) != 1)
+        rc = GM_EIO;
+    else if (memcmp(magic, kWarmMagic, 8) != 0 || dk[0] != 3 || dk[1] < 1 || dk[1] > 16 || np != gm::NPARAM)
+        rc = GM_EINVAL;  // not a model file of this library, or of another layout
+    else if (fread(h.data(), 4, h.size(), f) != h.size() || fgetc(f) != EOF)
+        rc = GM_EIO;     // truncated, or trailing bytes
+    fclose(f);
+    if (rc != GM_OK) return rc;
+    gm_warm* m = nullptr;
+    rc = gm_warm_create(&m, dk[0], dk[1], batch, 0, stream);
+    if (rc != GM_OK) return rc;
+    rc = gm_warm_set_params(m, h.data());
+    if (rc != GM_OK) {
+        gm_warm_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return GM_OK;
 }
 
 int gm_warm_features(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, int32_t D,

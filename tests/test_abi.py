@@ -121,3 +121,29 @@ def test_launch_plan_codes_checked_on_host():
     assert setp(c) == -1
     c[9] = 2 * 1000 + 16 * 10 + 3
     assert setp(c, fp64=1) == -1   # lean builds are FP32 only
+
+
+def test_warm_model_files_checked_before_any_device_work(tmp_path):
+    """gm_warm_load reads and checks the whole file before it allocates:
+    missing or truncated files are GM_EIO, foreign ones GM_EINVAL."""
+    import struct
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    load = lambda p: lib.gm_warm_load(ctypes.byref(h), os.fsencode(str(p)), 64, None)
+    assert load(tmp_path / "missing.bin") == _lib.GM_EIO
+    npar = lib.gm_warm_param_count()
+    good_head = b"GMCRWRM1" + struct.pack("<iiQ", 3, 16, npar)
+    (tmp_path / "short.bin").write_bytes(good_head + b"\0" * (4 * npar - 4))
+    assert load(tmp_path / "short.bin") == _lib.GM_EIO
+    (tmp_path / "long.bin").write_bytes(good_head + b"\0" * (4 * npar + 1))
+    assert load(tmp_path / "long.bin") == _lib.GM_EIO
+    for bad in (b"GMCRWRM2" + good_head[8:], b"GMCRWRM1" + struct.pack("<iiQ", 1, 16, npar),
+                b"GMCRWRM1" + struct.pack("<iiQ", 3, 17, npar), b"GMCRWRM1" + struct.pack("<iiQ", 3, 16, npar + 1)):
+        (tmp_path / "bad.bin").write_bytes(bad + b"\0" * (4 * npar))
+        assert load(tmp_path / "bad.bin") == _lib.GM_EINVAL
+    assert lib.gm_warm_load(ctypes.byref(h), os.fsencode(str(tmp_path / "short.bin")), 0, None) == _lib.GM_EINVAL
+    assert lib.gm_warm_save(None, os.fsencode(str(tmp_path / "x.bin"))) == _lib.GM_EINVAL
+    assert lib.gm_strerror(_lib.GM_EIO) == b"file could not be opened, read or written"

@@ -121,6 +121,27 @@ def test_forward_matches_oracle_bf16():
     m.close()
 
 
+def test_model_file_round_trip(tmp_path):
+    """gm_warm_save then gm_warm_load gives the same parameters bit for bit
+    and the same network outputs; the loaded model trains on."""
+    api = _api()
+    d = _subset(synth.make("weibel_3v"), 200)
+    f, _, _ = _oracle_feature_bits(d)
+    m = api.WarmStart(16, batch=64, seed=1)
+    m.set_params(api.params_to_flat(_params(23)))
+    path = tmp_path / "model.gmw"
+    m.save(path)
+    assert path.stat().st_size == 8 + 4 + 4 + 8 + 4 * m.n_param
+    m2 = api.WarmStart.load(path, batch=32)
+    assert m2.kmax == 16
+    np.testing.assert_array_equal(m2.get_params(), m.get_params())
+    y1, y2 = m.forward(f), m2.forward(f)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    m.close()
+    m2.close()
+
+
 def test_train_step_matches_oracle_gradients_and_adam():
     api = _api()
     B = 200
