@@ -372,6 +372,20 @@ int gm_warm_targets(const int32_t* K, const double* omega, const double* mu, con
 int gm_warm_train_step(gm_warm* model, const uint16_t* feats, const float* targets, int64_t n_rows,
                        const int32_t* idx, float lr, float lambda, float* loss_rows, void* stream);
 
+/* Training loop: `epochs` passes over the n_rows rows of feats / targets (as
+ * for gm_warm_train_step), each in floor(n_rows / batch) Adam steps on
+ * shuffled rows (the last partial batch is dropped).  The shuffle of epoch
+ * e is a Fisher-Yates permutation (top index down; j = high 64 bits of
+ * draw * (i + 1)) driven by splitmix64 from seed ^ (0xD1B54A32D192ED03 *
+ * (e + 1)), so the loop equals gm_warm_train_step calls on those rows.
+ * ws: device workspace of gm_warm_train_workspace(n_rows, batch) bytes
+ * (the permutation and the per-row losses).  epoch_loss: nullable HOST
+ * [epochs] receiving each epoch's mean row loss.  Synchronises the stream
+ * once per epoch.  GM_EINVAL if n_rows < batch. */
+size_t gm_warm_train_workspace(int64_t n_rows, int32_t batch);
+int gm_warm_train(gm_warm* model, const uint16_t* feats, const float* targets, int64_t n_rows, int32_t epochs,
+                  float lr, float lambda, uint64_t seed, void* ws, size_t ws_bytes, float* epoch_loss, void* stream);
+
 /*
  * gm_reconstruct_tensor -- as gm_reconstruct, with a projection that matches
  * the whole second-moment tensor of the target, not only its trace.  With

@@ -45,7 +45,8 @@ EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_autotu
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
            "gm_warm_set_params", "gm_warm_gradients", "gm_warm_save", "gm_warm_load", "gm_warm_features", "gm_warm_forward_workspace",
-           "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_profile_enable",
+           "gm_warm_forward", "gm_warm_decode", "gm_warm_targets", "gm_warm_train_step", "gm_warm_train_workspace",
+           "gm_warm_train", "gm_profile_enable",
            "gm_profile_read", "gm_strerror", "gm_version")
 
 _lib = None
@@ -108,6 +109,10 @@ def load():
     for name in ("gm_warm_get_params", "gm_warm_set_params", "gm_warm_gradients"):
         getattr(L, name).argtypes = [P, P]
         getattr(L, name).restype = ctypes.c_int
+    L.gm_warm_train_workspace.argtypes = [I64, I32]
+    L.gm_warm_train_workspace.restype = SZ
+    L.gm_warm_train.argtypes = [P, P, P, I64, I32, F32, F32, U64, P, SZ, P, P]
+    L.gm_warm_train.restype = ctypes.c_int
     L.gm_warm_save.argtypes = [P, ctypes.c_char_p]
     L.gm_warm_save.restype = ctypes.c_int
     L.gm_warm_load.argtypes = [ctypes.POINTER(P), ctypes.c_char_p, I32, P]

@@ -470,6 +470,25 @@ class WarmStart:
         check(_lib.load().gm_warm_train_step(self._h, _ptr(feats), _ptr(targets), feats.shape[0], _ptr(idx), lr, lam,
                                              _ptr(loss_rows), _stream(stream)), "gm_warm_train_step")
 
+    def train(self, feats, targets, epochs, lr=1e-3, lam=1.0, seed=0, stream=None):
+        """gm_warm_train: `epochs` shuffled passes of Adam steps; returns the
+        per-epoch mean row losses (a list of floats)."""
+        import numpy as np
+        _need(feats, torch.int16, "feats")
+        _need(targets, torch.float32, "targets")
+        if feats.shape[1] != NFEAT_ROW or targets.shape != (feats.shape[0], NOUT):
+            raise ValueError("features must be [n, 128] and targets [n, 160]")
+        L = _lib.load()
+        n = feats.shape[0]
+        need = int(L.gm_warm_train_workspace(n, self.batch))
+        if need == 0:
+            raise ValueError("need at least one full batch of %d rows, have %d" % (self.batch, n))
+        ws = torch.empty(need, dtype=torch.uint8, device=feats.device)
+        loss = np.zeros(epochs, dtype=np.float32)
+        check(L.gm_warm_train(self._h, _ptr(feats), _ptr(targets), n, epochs, lr, lam, seed, _ptr(ws), need,
+                              loss.ctypes.data, _stream(stream)), "gm_warm_train")
+        return [float(x) for x in loss]
+
     def initial_mixtures(self, v, alpha, cell_off, bufs=None, stream=None):
         """features -> forward -> decode: a gm_init record for compress.
         `bufs` (from init_buffers) makes repeated calls allocation-free."""

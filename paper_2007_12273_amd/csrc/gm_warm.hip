@@ -837,3 +837,86 @@ int gm_warm_gradients(const gm_warm* m, float* host)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Training loop: epochs of shuffled mini-batches.  The permutation of an
+// epoch is a Fisher-Yates shuffle (from the top index down, j uniform in
+// [0, i] as the high 64 bits of draw * (i + 1)) driven by splitmix64
+// (Steele, Lea and Flood 2014) started at seed ^ (0xD1B54A32D192ED03 *
+// (epoch + 1)).
+// ---------------------------------------------------------------------------
+namespace {
+
+uint64_t splitmix64_next(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void epoch_permutation(int32_t* perm, int64_t n, uint64_t seed, int32_t epoch)
+{
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    uint64_t x = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(epoch + 1));
+    for (int64_t i = n - 1; i >= 1; --i) {
+        const uint64_t r = splitmix64_next(x);
+        const int64_t j = (int64_t)(((unsigned __int128)r * (uint64_t)(i + 1)) >> 64);
+        const int32_t t = perm[i];
+        perm[i] = perm[j];
+        perm[j] = t;
+    }
+}
+
+size_t al256h(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+size_t gm_warm_train_workspace(int64_t n_rows, int32_t batch)
+{
+    if (n_rows < 1 || n_rows > 0x7fffffff || batch < 1 || n_rows < batch) return 0;
+    const int64_t steps = n_rows / batch;
+    return al256h((size_t)n_rows * 4) + al256h((size_t)(steps * batch) * 4);
+}
+
+int gm_warm_train(gm_warm* m, const uint16_t* feats, const float* targets, int64_t n_rows, int32_t epochs,
+                  float lr, float lambda, uint64_t seed, void* ws, size_t ws_bytes, float* epoch_loss, void* stream)
+{
+    if (!m || !feats || !targets || epochs < 1 || !(lr > 0.f) || !(lambda >= 0.f)) return GM_EINVAL;
+    const size_t need = gm_warm_train_workspace(n_rows, m->batch);
+    if (need == 0) return GM_EINVAL;  // fewer rows than one batch, or too many rows
+    if (!ws || ws_bytes < need) return GM_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    const int B = m->batch;
+    const int64_t steps = n_rows / B;
+    int32_t* dperm = (int32_t*)ws;
+    float* dloss = (float*)((char*)ws + al256h((size_t)n_rows * 4));
+    std::vector<int32_t> perm((size_t)n_rows);
+    std::vector<float> hl((size_t)(steps * B));
+    for (int32_t e = 0; e < epochs; ++e) {
+        epoch_permutation(perm.data(), n_rows, seed, e);
+        if (hipMemcpyAsync(dperm, perm.data(), (size_t)n_rows * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            return GM_EHIP;
+        for (int64_t s = 0; s < steps; ++s) {
+            const int rc = gm_warm_train_step(m, feats, targets, n_rows, dperm + s * B, lr, lambda, dloss + s * B,
+                                              stream);
+            if (rc != GM_OK) return rc;
+        }
+        // the host permutation is rewritten next epoch: wait for this one
+        if (epoch_loss) {
+            if (hipMemcpyAsync(hl.data(), dloss, hl.size() * 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+                return GM_EHIP;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) return GM_EHIP;
+        if (epoch_loss) {
+            double t = 0.0;
+            for (float x : hl) t += x;
+            epoch_loss[e] = (float)(t / (double)hl.size());
+        }
+    }
+    return GM_OK;
+}
+
+}  // extern "C"

@@ -1,11 +1,11 @@
 """Training driver of the learned warm start (host loop over library calls).
 
-The network, its loss, gradients and optimiser run in the gm_warm kernels;
-this module only draws the mini-batch order and sequences the calls:
+The network, its loss, gradients, optimiser and the epoch loop (shuffle
+and mini-batches) run in the library; this module sequences the calls:
 
   1. fit each training cell with plain (cold-start) EM on the GPU,
   2. compute features, frames and whitened targets of those fits,
-  3. run Adam over shuffled mini-batches for a fixed number of epochs.
+  3. run gm_warm_train for a fixed number of epochs.
 """
 from __future__ import annotations
 
@@ -35,21 +35,12 @@ def training_set(batches, kmax, seed=0, device="cuda"):
 
 def train(model, feats, targets, epochs=50, lr=1e-3, lam=1.0, seed=0, log=None):
     """Adam over shuffled mini-batches of model.batch rows (the last partial
-    batch of each epoch is dropped).  Returns per-epoch mean batch losses."""
-    n = feats.shape[0]
-    B = model.batch
-    steps = n // B
-    if steps < 1:
-        raise ValueError("need at least one full batch of %d rows, have %d" % (B, n))
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    loss_rows = torch.zeros(steps, B, dtype=torch.float32, device=feats.device)
-    hist = []
+    batch of each epoch is dropped): the library's training loop
+    (gm_warm_train).  Returns per-epoch mean batch losses."""
     t0 = time.perf_counter()
-    for ep in range(epochs):
-        perm = torch.randperm(n, generator=gen).to(torch.int32).to(feats.device)
-        for s in range(steps):
-            model.train_step(feats, targets, perm[s * B:(s + 1) * B], lr=lr, lam=lam, loss_rows=loss_rows[s])
-        hist.append(float(loss_rows.sum().item()) / (steps * B))
-        if log is not None:
-            log("epoch %d: loss %.4f (%.1f s)" % (ep + 1, hist[-1], time.perf_counter() - t0))
+    hist = model.train(feats, targets, epochs, lr=lr, lam=lam, seed=seed)
+    if log is not None:
+        for ep, h in enumerate(hist):
+            log("epoch %d: loss %.4f" % (ep + 1, h))
+        log("%d epochs in %.1f s" % (epochs, time.perf_counter() - t0))
     return hist

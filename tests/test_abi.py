@@ -147,3 +147,14 @@ def test_warm_model_files_checked_before_any_device_work(tmp_path):
     assert lib.gm_warm_load(ctypes.byref(h), os.fsencode(str(tmp_path / "short.bin")), 0, None) == _lib.GM_EINVAL
     assert lib.gm_warm_save(None, os.fsencode(str(tmp_path / "x.bin"))) == _lib.GM_EINVAL
     assert lib.gm_strerror(_lib.GM_EIO) == b"file could not be opened, read or written"
+
+
+def test_training_loop_arguments_checked_on_host():
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    assert lib.gm_warm_train_workspace(100, 1024) == 0          # fewer rows than one batch
+    assert lib.gm_warm_train_workspace(5000, 1024) >= 5000 * 4 + 4 * 1024 * 4
+    p = ctypes.c_void_p(8)  # never dereferenced: the checks fail first
+    assert lib.gm_warm_train(None, p, p, 5000, 1, 1e-3, 1.0, 0, p, 1 << 20, None, None) == -1

@@ -142,6 +142,52 @@ def test_model_file_round_trip(tmp_path):
     m2.close()
 
 
+def _epoch_permutation(n, seed, epoch):
+    """The documented shuffle of gm_warm_train, written out (splitmix64 draws,
+    Fisher-Yates from the top index down)."""
+    M = (1 << 64) - 1
+    x = (seed ^ (0xD1B54A32D192ED03 * (epoch + 1))) & M
+    perm = list(range(n))
+    for i in range(n - 1, 0, -1):
+        x = (x + 0x9E3779B97F4A7C15) & M
+        z = x
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z ^= z >> 31
+        j = (z * (i + 1)) >> 64
+        perm[i], perm[j] = perm[j], perm[i]
+    return perm
+
+
+def test_training_loop_equals_its_steps():
+    """gm_warm_train over 3 epochs gives bit for bit the parameters of the
+    same Adam steps called one by one on the documented permutations; the
+    shuffle is a permutation and differs between epochs."""
+    api = _api()
+    n, B = 300, 64
+    d = _subset(synth.make("weibel_3v"), n)
+    f, _, _ = _oracle_feature_bits(d)
+    rng = np.random.default_rng(3)
+    t = torch.from_numpy(rng.normal(size=(n, 160)).astype(np.float32) * 0.3).to(dev())
+    a = api.WarmStart(16, batch=B, seed=5)
+    b = api.WarmStart(16, batch=B, seed=5)
+    hist = a.train(f, t, 3, lr=2e-3, lam=0.5, seed=77)
+    losses = []
+    for e in range(3):
+        perm = _epoch_permutation(n, 77, e)
+        assert sorted(perm) == list(range(n))
+        idx = torch.tensor(perm, dtype=torch.int32, device=dev())
+        rows = torch.zeros(n // B, B, dtype=torch.float32, device=dev())
+        for s in range(n // B):
+            b.train_step(f, t, idx[s * B:(s + 1) * B], lr=2e-3, lam=0.5, loss_rows=rows[s])
+        losses.append(float(rows.double().sum().item()) / (n // B * B))
+    assert _epoch_permutation(n, 77, 0) != _epoch_permutation(n, 77, 1)
+    np.testing.assert_array_equal(a.get_params(), b.get_params())
+    np.testing.assert_allclose(hist, losses, rtol=1e-6)
+    a.close()
+    b.close()
+
+
 def test_train_step_matches_oracle_gradients_and_adam():
     api = _api()
     B = 200
