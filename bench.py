@@ -50,6 +50,10 @@ WORKLOADS = {
         D=3, kmax=8, dx=2, init_seed=2004, recon_seed=3004,
         desc="2D3V grid: 65536 cells, log-normal counts mean 256 (2^24 particles), 1-4 isotropic Maxwellians, "
              "weights U(0.5,1.5), kmax 8; compress + reconstruct n' = n, dx = 2"),
+    "two_stream_1v": dict(
+        D=1, kmax=8, dx=1, init_seed=2001, recon_seed=3001, fp64=True,
+        desc="1D1V two-stream: 32 cells x 1000 equal-weight particles, two Maxwellians drifting +-0.2 with vth "
+             "0.05, kmax 8; FP64 EM iterations; compress to convergence + reconstruct n' = n, dx = 1"),
     "mix_1v": dict(
         D=1, kmax=8, dx=1, init_seed=2002, recon_seed=3002,
         desc="1D1V: 1024 cells, counts max(200, Poisson(2000)), 1-4 Maxwellians, weights U(0.5,1.5), kmax 8 "
@@ -57,6 +61,7 @@ WORKLOADS = {
 }
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64, published
 # algorithmic flops per (particle, component update), transcendentals as 1:
 # density 19 + exp 1 + denominator 5 + responsibility 2 + moment sums 22 in 3V
 FLOPS_PER_UPDATE = {3: 49, 1: 18}
@@ -87,8 +92,9 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="weibel_3v", choices=sorted(WORKLOADS))
-    p.add_argument("--start", default="warm", choices=("warm", "cold"),
-                   help="warm: learned warm start (the headline); cold: plain EM only")
+    p.add_argument("--start", default="auto", choices=("auto", "warm", "cold"),
+                   help="warm: learned warm start (the headline); cold: plain EM only; auto: warm for weibel_3v "
+                        "(the network's training distribution), cold otherwise")
     p.add_argument("--train-sets", type=int, default=16, help="training batches of cells (seeds 5000+i)")
     p.add_argument("--epochs", type=int, default=50)
     p.add_argument("--cpu-cells", type=int, default=512, help="cells in the CPU-oracle sample (512 evenly spaced cells of the Weibel-like batch: about 15 s on 16 host threads)")
@@ -243,12 +249,37 @@ def standard_em_report(v, alpha, off, D, kmax, W, reps, api, torch):
     return out
 
 
+def conservation(recon, moments, counts, D, torch):
+    """Largest relative error of the reconstructed particles' mass, momentum
+    and energy against each cell's moments record, over the cells the
+    projection ran on (momentum on the thermal scale sqrt(2 W E))."""
+    import numpy as np
+    dev = recon.w.device
+    n_cells = len(counts)
+    cell = torch.repeat_interleave(torch.arange(n_cells, device=dev), torch.from_numpy(counts).to(dev))
+    v = recon.v.reshape(-1, D)
+    w = recon.w
+    Wc = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell, w)
+    Pc = torch.zeros(n_cells, D, dtype=torch.float64, device=dev).index_add_(0, cell, w[:, None] * v)
+    Ec = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell, 0.5 * w * (v * v).sum(1))
+    m = torch.from_numpy(moments).to(dev) if isinstance(moments, np.ndarray) else moments
+    diag = [i * D - i * (i - 1) // 2 for i in range(D)]
+    Wt, Pt, Et = m[:, 0], m[:, 1:1 + D], 0.5 * m[:, 1 + D:][:, diag].sum(1)
+    ok = ((recon.status & 128) == 0) & (torch.from_numpy(counts).to(dev) > 0) & (Wt > 0) & (Et > 0)
+    eW = ((Wc - Wt).abs() / Wt)[ok]
+    eP = ((Pc - Pt).abs().max(1).values / (2.0 * Wt * Et).sqrt())[ok]
+    eE = ((Ec - Et).abs() / Et)[ok]
+    return {"max_rel_err": float(torch.stack([eW.max(), eP.max(), eE.max()]).max().item()) if ok.any() else None,
+            "cells_checked": int(ok.sum().item()), "lemons_skipped": int(((recon.status & 128) != 0).sum().item())}
+
+
 def outer_k_search(v, alpha, off, D, kmax, W, cold, reps, api, torch):
     """The cold compress with the outer search over K (gm_opts.outer_k),
     against the single pass of the same start: time, K, penalised L."""
     import numpy as np
     n_cells = off.numel() - 1
-    comp = api.Compressor(n_cells, D, kmax, device=off.device, seed=W["init_seed"], outer_k=True)
+    comp = api.Compressor(n_cells, D, kmax, device=off.device, seed=W["init_seed"], outer_k=True,
+                          fp64=bool(W.get("fp64", False)))
     ms = time_steps(lambda: comp(v, alpha, off), reps, 1, torch)
     o = {k: t.cpu().numpy() for k, t in comp.out.as_dict().items()}
     ok = np.isfinite(o["L_pen"]) & np.isfinite(cold["L_pen"])
@@ -318,7 +349,8 @@ def main():
               "sharding plan is a contiguous split of the cell list per GPU). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     W = WORKLOADS[args.workload]
-    warm = args.start == "warm"
+    warm = args.start == "warm" or (args.start == "auto" and args.workload == "weibel_3v")
+    fp64 = bool(W.get("fp64", False))
     if warm and W["D"] != 3:
         raise SystemExit("the learned warm start is built for 3V workloads; use --start cold")
     train_sets = []
@@ -343,8 +375,8 @@ def main():
     counts = np.diff(data["cell_off"])
     D, kmax, dx = W["D"], W["kmax"], W["dx"]
 
-    comp_c = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"])
-    comp_w = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"])
+    comp_c = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
+    comp_w = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
     recon = api.Reconstructor(off, D, dx, device=dev)
 
     model = None
@@ -423,7 +455,7 @@ def main():
         judged = np.nonzero(rel < -JUDGE_REL)[0]
         # calibration of the protocol: a cold fit from another random start,
         # judged against the same cold fit
-        comp_r = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"] + 7919)
+        comp_r = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"] + 7919, fp64=fp64)
         rr = {k: t.cpu().numpy() for k, t in comp_r(v, alpha, off).as_dict().items()}
         ok2 = np.isfinite(rr["L_pen"]) & np.isfinite(cold["L_pen"])
         rel2 = (rr["L_pen"][ok2] - cold["L_pen"][ok2]) / np.abs(cold["L_pen"][ok2])
@@ -431,7 +463,7 @@ def main():
         ms_extra = 0.0
         if len(judged):
             sv, sa, so = subset_gpu(v, alpha, data["cell_off"], judged, torch)
-            comp_s = api.Compressor(len(judged), D, kmax, device=dev, seed=W["init_seed"])
+            comp_s = api.Compressor(len(judged), D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
             ms_extra = time_steps(lambda: comp_s(sv, sa, so), max(1, args.steps), 1, torch)
         ms = ms_warm + ms_extra
         em_ms, visits = ph_warm["em"], wr["visits"]
@@ -472,6 +504,8 @@ def main():
     tr = EM_TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if (warm and tr and tr["sources_sha256"] == em_sources_digest()) else None
     achieved = em_flops / (em_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    cons = conservation(recon, wr["moments"], counts, D, torch)
     recon_bytes = n_part * 8 * (D + 1 + dx)
     line = {
         "metric": METRIC,
@@ -484,21 +518,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
         "config": {
             "workload": args.workload + ": " + W["desc"],
             "cells": n_cells, "particles": n_part, "kmax": kmax, "D": D,
             "start": "learned warm start (judged fallback to cold counted)" if warm else "cold (plain EM)",
-            "precision": "EM sweeps f32; moments, finish, reconstruct f64; perceptron bf16 x bf16 -> f32",
+            "precision": ("EM sweeps f64" if fp64 else "EM sweeps f32") + "; moments, finish, reconstruct f64"
+                         + ("; perceptron bf16 x bf16 -> f32" if warm else ""),
         },
         "roofline": {
             "kernel": "k_em (all length buckets, one EM phase)",
             "bound": "alu",
             "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac": achieved / peak,
             "traffic": traffic,
             "traffic_plan": EM_TRAFFIC[args.workload]["plan"] if traffic is not None else None,
             "flops_per_launch": em_flops,
@@ -511,6 +546,7 @@ def main():
         "mean_sweeps": float(wr["sweeps"].mean()),
         # the paper's ratio: particles per Gaussian component
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
+        "conservation": cons,
     }
     line.update(line_extra)
     if not args.no_standard:
