@@ -572,7 +572,9 @@ int launch_std_d(const StdArgs& p, int64_t n_cells, hipStream_t st)
 {
     if (n_cells == 0) return 0;
     hipLaunchKernelGGL(k_std_stage<D>, dim3((unsigned)n_cells), dim3(256), 0, st, p);
-    if (p.a.kmax <= 8)
+    // the component count fixes the register arrays: K <= 8 runs the 8-slot
+    // kernel whatever kmax the output record is padded to
+    if (p.K <= 8)
         hipLaunchKernelGGL((k_std<D, 8>), dim3((unsigned)n_cells), dim3(kStdThreads), 0, st, p);
     else
         hipLaunchKernelGGL((k_std<D, 16>), dim3((unsigned)n_cells), dim3(kStdThreads), 0, st, p);
