@@ -139,7 +139,15 @@ __global__ __launch_bounds__(kStdThreads) void k_std(StdArgs P)
 #pragma unroll
             for (int j = i; j < D; ++j) t[1 + D + tri_idx<D>(i, j)] = (double)S[tri_idx<D>(i, j)] + mu[i] * mu[j];
     };
-    auto wsum = [&](double x) -> double { return wave_sum(x); };
+    // sums over the component lanes of wave 0 (lane k holds component k,
+    // lanes from K on hold zeros): the tree of the first 8 or 16 lanes
+    auto wsum = [&](double x) -> double {
+        x += dpp_d<0xB1>(x);   // quad_perm [1,0,3,2]
+        x += dpp_d<0x4E>(x);   // quad_perm [2,3,0,1]
+        x += dpp_d<0x141>(x);  // row_half_mirror: 8-lane totals
+        if constexpr (KMAX > 8) x += dpp_d<0x140>(x);  // row_mirror: 16-lane totals
+        return lane_bcast(x, 0);
+    };
     for (int t = tid; t < 2 * kMaxWaves * NKM; t += kStdThreads) red_d[t] = 0.0;
     __syncthreads();
 
