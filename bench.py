@@ -345,7 +345,7 @@ def subset_gpu(v, alpha, off_host, cells, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: cells are independent and this build has no multi-GPU path (the "
+        print("bench.py measures one GPU: cells are independent and the library has no multi-GPU path (the "
               "sharding plan is a contiguous split of the cell list per GPU). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     W = WORKLOADS[args.workload]
