@@ -255,13 +255,14 @@ def conservation(recon, moments, counts, D, torch):
     projection ran on (momentum on the thermal scale sqrt(2 W E))."""
     import numpy as np
     dev = recon.w.device
-    n_cells = len(counts)
-    cell = torch.repeat_interleave(torch.arange(n_cells, device=dev), torch.from_numpy(counts).to(dev))
+    lengths = torch.from_numpy(counts).to(dev)
     v = recon.v.reshape(-1, D)
     w = recon.w
-    Wc = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell, w)
-    Pc = torch.zeros(n_cells, D, dtype=torch.float64, device=dev).index_add_(0, cell, w[:, None] * v)
-    Ec = torch.zeros(n_cells, dtype=torch.float64, device=dev).index_add_(0, cell, 0.5 * w * (v * v).sum(1))
+    # per-cell sums over the cells' contiguous particle ranges
+    seg = lambda x: torch.segment_reduce(x, "sum", lengths=lengths, axis=0)
+    Wc = seg(w)
+    Pc = seg(w[:, None] * v)
+    Ec = seg(0.5 * w * (v * v).sum(1))
     m = torch.from_numpy(moments).to(dev) if isinstance(moments, np.ndarray) else moments
     diag = [i * D - i * (i - 1) // 2 for i in range(D)]
     Wt, Pt, Et = m[:, 0], m[:, 1:1 + D], 0.5 * m[:, 1 + D:][:, diag].sum(1)
