@@ -114,24 +114,26 @@ __host__ __device__ inline int bucket_of(int kmax_tpl, int n)
 }
 
 // ===========================================================================
-// k_moments
+// k_moments: one wave per cell (kMomCellsPerBlock cells per workgroup), no
+// workgroup barrier; fixed-order DPP wave sums
 // ===========================================================================
+constexpr int kMomCellsPerBlock = 4;
+
 template <int D>
-__global__ __launch_bounds__(256) void k_moments(CompressArgs A)
+__global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs A)
 {
     constexpr int NT = ntri(D);
     constexpr int NM = nmom(D);
-    __shared__ double red[2 * kMaxWaves * (NM + 1)];
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x, nthreads = blockDim.x, nwaves = nthreads >> 6;
-    int par = 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * kMomCellsPerBlock + (threadIdx.x >> 6);
+    if (c >= A.n_cells) return;  // whole waves leave
     const int64_t o0 = A.off[c];
     const int64_t n64 = A.off[c + 1] - o0;
     CellInfo<D>* ci = static_cast<CellInfo<D>*>(A.cells) + c;
     double* mom = A.out.moments + (size_t)c * NM;
     if (n64 <= 0 || n64 > kMaxCellParticles) {
-        if (tid < NM) mom[tid] = 0.0;
-        if (tid == 0) {
+        if (lane < NM) mom[lane] = 0.0;
+        if (lane == 0) {
             ci->kind = n64 == 0 ? CELL_EMPTY : CELL_OVERSIZE;
             ci->n = 0;
         }
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
     double acc[NM + 1];
 #pragma unroll
     for (int t = 0; t < NM + 1; ++t) acc[t] = 0.0;
-    for (int i = tid; i < n; i += nthreads) {
+    for (int i = lane; i < n; i += 64) {
         const double al = ac[i];
         double x[D];
 #pragma unroll
@@ -160,16 +162,19 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
 #pragma unroll
             for (int b = a; b < D; ++b) acc[1 + D + tri_idx<D>(a, b)] += al * x[a] * x[b];
     }
-    block_sum<NM + 1>(acc, red, par, nwaves);
+#pragma unroll
+    for (int t = 0; t < NM + 1; ++t) acc[t] = wave_sum(acc[t]);
     if (acc[NM] > 0.0) {
-        if (tid < NM) mom[tid] = 0.0;
-        if (tid == 0) {
+        if (lane < NM) mom[lane] = 0.0;
+        if (lane == 0) {
             ci->kind = CELL_INVALID;
             ci->n = n;
         }
         return;
     }
-    if (tid < NM) mom[tid] = acc[tid];
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+        if (lane == t) mom[t] = acc[t];
     const double W = acc[0];
     double m[D];
 #pragma unroll
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
     double cov[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cov[t] = 0.0;
-    for (int i = tid; i < n; i += nthreads) {
+    for (int i = lane; i < n; i += 64) {
         const double al = ac[i];
         double x[D];
 #pragma unroll
@@ -187,64 +192,70 @@ __global__ __launch_bounds__(256) void k_moments(CompressArgs A)
 #pragma unroll
             for (int b = a; b < D; ++b) cov[tri_idx<D>(a, b)] += al * x[a] * x[b];
     }
-    block_sum<NM + 1>(cov, red, par, nwaves);
-    if (tid == 0) {
-        double C[NT], L[NT], tr = 0.0;
-        for (int t = 0; t < NT; ++t) C[t] = cov[t] / W;
-        for (int d = 0; d < D; ++d) tr += C[tri_idx<D>(d, d)];
-        const bool spd = chol<D, double>(C, L);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cov[t] = wave_sum(cov[t]);
+    double C[NT], L[NT], tr = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) C[t] = cov[t] / W;
+#pragma unroll
+    for (int d = 0; d < D; ++d) tr += C[tri_idx<D>(d, d)];
+    const bool spd = chol<D, double>(C, L);
+    const bool closed = n <= A.n_min || !spd;
+    if (lane == 0) {
         for (int d = 0; d < D; ++d) ci->m[d] = m[d];
         for (int t = 0; t < NT; ++t) ci->C[t] = C[t];
         ci->trC = tr;
         ci->W = W;
         ci->n = n;
-        const bool closed = n <= A.n_min || !spd;
         ci->kind = closed ? CELL_CLOSED : CELL_EM;
-        if (!closed) {
-            atomicAdd(&A.plan[PLAN_COUNT + bucket_of(A.kmax <= 8 ? 8 : 16, n)], 1);
-            // cold start: min(kmax, n, floor(N/T)) distinct particles by a
-            // partial Fisher-Yates draw; draw j swaps positions j and
-            // j + floor(x (n - j) / 2^64), x the first word of Philox with key
-            // (seed, "INIT") and counter (j, cell, 0, 0).  The permutation is
-            // kept as a sparse record of the swapped positions.
-            const double T = 0.5 * D * (D + 3);
-            int K = min(A.std_K > 0 ? A.std_K : A.kmax, n);
-            const int cap = max(1, (int)floor((double)n / T));
-            if (A.std_K == 0 && K > cap) K = cap;
-            int pos[2 * kInitSlots], val[2 * kInitSlots], nrec = 0;
-            for (int j = 0; j < K; ++j) {
-                const u64x4 r = philox4x64_10((uint64_t)j, (uint64_t)c, 0, 0, A.seed, kTagInit);
-                const int rr = j + (int)__umul64hi(r.x, (uint64_t)(n - j));
-                int vr = rr, vj = j, tr = -1, tj = -1;
-                for (int t = 0; t < nrec; ++t) {
-                    if (pos[t] == rr) {
-                        vr = val[t];
-                        tr = t;
-                    }
-                    if (pos[t] == j) {
-                        vj = val[t];
-                        tj = t;
-                    }
-                }
-                if (tj < 0) {
-                    tj = nrec++;
-                    pos[tj] = j;
-                }
-                val[tj] = vr;
-                if (rr != j) {
-                    if (tr < 0) {
-                        tr = nrec++;
-                        pos[tr] = rr;
-                    }
-                    val[tr] = vj;
-                }
-                A.init_idx[(size_t)c * kInitSlots + j] = vr;
+        if (!closed) atomicAdd(&A.plan[PLAN_COUNT + bucket_of(A.kmax <= 8 ? 8 : 16, n)], 1);
+    }
+    if (closed) return;
+    // cold start: min(kmax, n, floor(N/T)) distinct particles by a partial
+    // Fisher-Yates draw; draw j swaps positions j and j + floor(x (n - j) /
+    // 2^64), x the first word of Philox with key (seed, "INIT") and counter
+    // (j, cell, 0, 0).  Lane j computes draw j; the swaps then run in order
+    // on every lane alike, the permutation kept as a sparse record of the
+    // swapped positions.
+    const double T = 0.5 * D * (D + 3);
+    int K = min(A.std_K > 0 ? A.std_K : A.kmax, n);
+    const int cap = max(1, (int)floor((double)n / T));
+    if (A.std_K == 0 && K > cap) K = cap;
+    int my_rr = 0;
+    if (lane < K) {
+        const u64x4 r = philox4x64_10((uint64_t)lane, (uint64_t)c, 0, 0, A.seed, kTagInit);
+        my_rr = lane + (int)__umul64hi(r.x, (uint64_t)(n - lane));
+    }
+    int pos[2 * kInitSlots], val[2 * kInitSlots], nrec = 0;
+    for (int j = 0; j < K; ++j) {
+        const int rr = __builtin_amdgcn_readlane(my_rr, j);
+        int vr = rr, vj = j, trr = -1, tj = -1;
+        for (int t = 0; t < nrec; ++t) {
+            if (pos[t] == rr) {
+                vr = val[t];
+                trr = t;
+            }
+            if (pos[t] == j) {
+                vj = val[t];
+                tj = t;
             }
         }
+        if (tj < 0) {
+            tj = nrec++;
+            pos[tj] = j;
+        }
+        val[tj] = vr;
+        if (rr != j) {
+            if (trr < 0) {
+                trr = nrec++;
+                pos[trr] = rr;
+            }
+            val[trr] = vj;
+        }
+        if (lane == 0) A.init_idx[(size_t)c * kInitSlots + j] = vr;
     }
 }
 
-// bucket bases and queue resets (one thread)
 static __global__ void k_plan_scan(int32_t* plan)
 {
     int base = 0;
@@ -1468,7 +1479,8 @@ template <int D>
 int launch_pre_dr(const CompressArgs& a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_plan_reset, dim3(1), dim3(64), 0, st, a.plan);
-    hipLaunchKernelGGL(k_moments<D>, dim3((unsigned)a.n_cells), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_moments<D>, dim3((unsigned)((a.n_cells + kMomCellsPerBlock - 1) / kMomCellsPerBlock)),
+                       dim3(64 * kMomCellsPerBlock), 0, st, a);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1), 0, st, a.plan);
     hipLaunchKernelGGL(k_plan_scatter<D>, dim3((unsigned)((a.n_cells + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
