@@ -267,17 +267,31 @@ static __global__ void k_plan_scan(int32_t* plan)
     }
 }
 
-// EM cells into their buckets
+// EM cells into their buckets: per wave, one atomic per distinct bucket
+// among its lanes (a cursor add of the group's size), and each lane's slot
+// is its rank within the group
 template <int D>
 __global__ void k_plan_scatter(CompressArgs A)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= A.n_cells) return;
-    const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
-    if (ci->kind != CELL_EM) return;
-    const int b = bucket_of(A.kmax <= 8 ? 8 : 16, ci->n);
-    const int pos = atomicAdd(&A.plan[PLAN_CURSOR + b], 1);
-    A.list[A.plan[PLAN_BASE + b] + pos] = (int32_t)c;
+    const int lane = threadIdx.x & 63;
+    int b = -1;
+    if (c < A.n_cells) {
+        const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+        if (ci->kind == CELL_EM) b = bucket_of(A.kmax <= 8 ? 8 : 16, ci->n);
+    }
+    uint64_t todo = __builtin_amdgcn_ballot_w64(b >= 0);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int bl = __builtin_amdgcn_readlane(b, leader);
+        const uint64_t group = __builtin_amdgcn_ballot_w64(b == bl);
+        int first = 0;
+        if (lane == leader) first = atomicAdd(&A.plan[PLAN_CURSOR + bl], __builtin_popcountll(group));
+        first = __builtin_amdgcn_readlane(first, leader);
+        if (b == bl) A.list[A.plan[PLAN_BASE + bl] + first + __builtin_popcountll(group & below)] = (int32_t)c;
+        todo &= ~group;
+    }
 }
 
 static __global__ void k_plan_reset(int32_t* plan)
