@@ -256,6 +256,7 @@ __global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs
     }
 }
 
+// bucket bases and queue resets (one thread)
 static __global__ void k_plan_scan(int32_t* plan)
 {
     int base = 0;
