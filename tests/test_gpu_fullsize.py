@@ -7,6 +7,8 @@ properties that hold for every cell.
   parameters, converged mode;
 * 2D3V grid (65536 cells, 2^24 particles, kmax 8, dx = 2), cold start,
   compress and reconstruct;
+* 1D1V mixed batch (1024 cells, kmax 1..8 distributions), cold start,
+  compress and reconstruct;
 * the restart chain at both sizes: deposit of the original particles,
   sampling, Gauss'-law weight correction, projection with the corrected
   mass; checked by brute-force deposits on sampled mesh cells and by the
@@ -73,7 +75,7 @@ def _all_cells_conserve(g, D):
     assert (np.abs(Sm - S).max(1) / tr).max() < 1e-12
 
 
-def _compare_sampled(g, d, cells, kmax, seed, label, init=None):
+def _compare_sampled(g, d, cells, kmax, seed, label, init=None, within=0.9):
     """Converged mode on sampled cells.  FP32 sweeps move the stopping sweep
     of slowly converging cells (the stop test compares L changes of 1e-7),
     so cells are compared whenever K agrees: L to 1e-4 relative (what the
@@ -106,7 +108,7 @@ def _compare_sampled(g, d, cells, kmax, seed, label, init=None):
     # the oracle's own parameters move by this much within 20-50 sweeps past
     # its stop (test_stop_rule_resolution): the scale to which a converged
     # fit is defined
-    assert np.median(errs) <= 2e-3 and (errs <= 3e-2).mean() >= 0.9
+    assert np.median(errs) <= 2e-3 and (errs <= 3e-2).mean() >= within
     return o
 
 
@@ -335,3 +337,41 @@ def test_weibel_full_size_standard_em_and_outer_search():
     print("outer search: K equal in %d / %d sampled cells, L error median %.1e" % (kk.sum(), len(cells),
                                                                                   np.median(eL[kk])))
     assert kk.mean() >= 0.85 and (eL[kk] <= 1e-4).mean() >= 0.9
+
+
+def test_mix_1v_full_size_compress_and_reconstruct():
+    """The 1D1V mixed batch (1024 cells, counts max(200, Poisson(2000)),
+    weights U(0.5, 1.5), kmax 8) at full size: every cell's mixture conserves
+    the moments, sampled cells against the oracle, and the reconstructed
+    particles' mass, momentum and energy in every projected cell."""
+    from paper_2007_12273_amd import api
+    d = synth.make("mix_1v")
+    n_cells = len(d["cell_off"]) - 1
+    assert n_cells == 1024
+    v, a, off = to_gpu(d)
+    comp = api.Compressor(n_cells, 1, 8, device=dev(), seed=2002)
+    r = comp(v, a, off)
+    rec = api.Reconstructor(off, 1, 1, device=dev())
+    out = rec(r.K, r.omega, r.mu, r.sigma, r.moments, 3002)
+    torch.cuda.synchronize()
+    g = host(r.as_dict())
+    _all_cells_conserve(g, 1)
+    rng = np.random.default_rng(41)
+    cells = sorted(set(rng.choice(n_cells, 24, replace=False).tolist()) | {0, n_cells - 1})
+    # most 1V cells stop at the 1000-sweep cap, where the parameters are
+    # still moving: 20 sweeps more move the oracle's own by a median of a few
+    # 1e-2 (test_sweep_cap_resolution_1v), so fewer cells are asked to agree
+    # within 3e-2 than for the converged 3V cells
+    _compare_sampled(g, d, cells, 8, 2002, "mix_1v cold", within=0.75)
+    ro = host(out)
+    offh = d["cell_off"]
+    tg = oracle.targets_from_moments(g["moments"], 1)
+    w, vv = ro["w"], ro["v"].reshape(-1)
+    W = np.add.reduceat(w, offh[:-1])
+    P = np.add.reduceat(w * vv, offh[:-1])
+    E = 0.5 * np.add.reduceat(w * vv * vv, offh[:-1])
+    ok = (ro["status"] & oracle.STATUS["LEMONS_SKIPPED"]) == 0
+    assert ok.mean() > 0.999
+    assert (np.abs(W - tg[:, 0]) / tg[:, 0]).max() < 1e-13
+    assert (np.abs(P - tg[:, 1])[ok] / np.sqrt(2 * tg[ok, 0] * tg[ok, 2])).max() < 1e-12
+    assert (np.abs(E - tg[:, 2])[ok] / tg[ok, 2]).max() < 1e-12
