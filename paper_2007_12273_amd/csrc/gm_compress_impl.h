@@ -1,7 +1,7 @@
 // gm_compress_impl.h -- per-cell adaptive EM-GM for gfx950.
 //
 // Three kernels per compress call (plus the length-bucket plan):
-//   k_moments  one workgroup per cell, FP64: W = sum alpha, P = sum alpha v,
+//   k_moments  one wave per cell, FP64: W = sum alpha, P = sum alpha v,
 //              S = sum alpha v v^T, mean m = P / W, covariance C about m (two
 //              passes); classifies the cell (invalid / empty / small or
 //              singular -> closed form / EM) and bins EM cells by length.
@@ -11,7 +11,8 @@
 //              VGPRs for the whole fit; LDS carries only the component
 //              parameters and the cross-wave partial sums.  Writes the
 //              converged penalised mixture into the output record.
-//   k_finish   one workgroup per cell, FP64: the unpenalised joint EM step
+//   k_finish   one wave (up to 512 particles) or one workgroup per cell, FP64:
+//              the unpenalised joint EM step
 //              (Sec. 2.3.1) or the single-Gaussian closed form, then the
 //              penalised log-likelihood of the output mixture.
 //
@@ -1177,21 +1178,53 @@ __device__ __forceinline__ bool make_f64(CompF64<D>& c, const double* mu, const 
 
 constexpr int kFinishThreads = 256;
 constexpr int kFinishCache = 2048;  // per-particle normalisers cached in LDS
+// cells of at most this many particles are finished by one wave each (four
+// per workgroup, no workgroup barrier); larger ones by a whole workgroup
+constexpr int kFinishWaveMax = 512;
+constexpr int kFinishCellsPerBlock = kFinishThreads / 64;
 
-template <int D, int KMAX>
+// orders one wave's LDS writes before its later LDS reads by other lanes
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int D, int KMAX, bool WAVE>
 __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
 {
     constexpr int NT = ntri(D);
     constexpr int NS = 1 + D + NT;
-    __shared__ CompF64<D> cf[KMAX];
-    __shared__ double outw[KMAX], outmu[KMAX][D], outS[KMAX][NT];
-    __shared__ double red[2 * kMaxWaves * NS];
-    __shared__ double mx_cache[kFinishCache], sum_cache[kFinishCache];
-    __shared__ int s_ok;
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x, nthreads = blockDim.x, nwaves = nthreads >> 6;
-    int par = 0;
+    constexpr int SLOTS = WAVE ? kFinishCellsPerBlock : 1;
+    constexpr int CACHE = WAVE ? kFinishWaveMax : kFinishCache;
+    __shared__ CompF64<D> cf_s[SLOTS][KMAX];
+    __shared__ double outw_s[SLOTS][KMAX], outmu_s[SLOTS][KMAX][D], outS_s[SLOTS][KMAX][NT];
+    __shared__ double red[WAVE ? 1 : 2 * kMaxWaves * NS];
+    __shared__ double mx_cache_s[SLOTS][CACHE], sum_cache_s[SLOTS][CACHE];
+    __shared__ int s_ok_s[SLOTS];
+    const int slot = WAVE ? (int)(threadIdx.x >> 6) : 0;
+    const int64_t c = WAVE ? (int64_t)blockIdx.x * kFinishCellsPerBlock + slot : (int64_t)blockIdx.x;
+    if (c >= A.n_cells) return;  // whole waves leave (wave mode only)
     const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+    // each cell is finished by exactly one of the two instantiations
+    if (WAVE ? ci->n > kFinishWaveMax : ci->n <= kFinishWaveMax) return;
+    CompF64<D>(&cf)[KMAX] = cf_s[slot];
+    double(&outw)[KMAX] = outw_s[slot];
+    double(&outmu)[KMAX][D] = outmu_s[slot];
+    double(&outS)[KMAX][NT] = outS_s[slot];
+    double* mx_cache = mx_cache_s[slot];
+    double* sum_cache = sum_cache_s[slot];
+    int& s_ok = s_ok_s[slot];
+    const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+    const int nthreads = WAVE ? 64 : (int)blockDim.x, nwaves = nthreads >> 6;
+    auto sync = [&]() {
+        if constexpr (WAVE)
+            wave_lds_sync();
+        else
+            __syncthreads();
+    };
+    int par = 0;
     const int kind = ci->kind;
     const int kmax = A.kmax;
     const double T = 0.5 * D * (D + 3);
@@ -1274,7 +1307,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             for (int q = 0; q < NT; ++q) outS[0][q] = ci->C[q];
             s_ok = make_f64<D>(cf[0], outmu[0], outS[0], 1.0);
         }
-        __syncthreads();
+        sync();
         if (!s_ok) status |= GM_ST_DEGENERATE;
         const double Lk = s_ok ? loglik(1) + penalty(1) : -INFINITY;
         L_pen = Lk;
@@ -1294,10 +1327,10 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             for (int q = 0; q < NT; ++q) S[q] = A.out.sigma[sk * NT + q];
             make_f64<D>(cf[tid], mu, S, A.out.omega[sk]);
         }
-        __syncthreads();
+        sync();
         // gamma_pk = a_p exp(l_k - mx_p) / sum_j exp(l_j - mx_p): a ratio of
         // the same exponentials, so sum_k gamma_pk = a_p to rounding
-        const bool cache = n <= kFinishCache;
+        const bool cache = n <= CACHE;
         if (cache) {
             for (int i = tid; i < n; i += nthreads) {
                 double xv[D];
@@ -1305,7 +1338,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
                 norm_at(xv, K, mx_cache[i], sum_cache[i]);
             }
         }
-        __syncthreads();
+        sync();
         for (int k = 0; k < K; ++k) {
             double sm[NS];
 #pragma unroll
@@ -1349,7 +1382,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
                 outw[k] = Nk / N;
             }
         }
-        __syncthreads();
+        sync();
         // the output must factor; otherwise the closed form replaces it
         if (tid == 0) {
             bool ok = true;
@@ -1362,7 +1395,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             }
             s_ok = ok;
         }
-        __syncthreads();
+        sync();
         if (!s_ok) {
             status |= GM_ST_DEGENERATE;
             K = 1;
@@ -1504,10 +1537,14 @@ int launch_pre_dr(const CompressArgs& a, hipStream_t st)
 template <int D>
 int launch_finish_dr(int kmax_tpl, const CompressArgs& a, hipStream_t st)
 {
-    if (kmax_tpl == 8)
-        hipLaunchKernelGGL((k_finish<D, 8>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_finish<D, 16>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
+    const unsigned nb_wave = (unsigned)((a.n_cells + kFinishCellsPerBlock - 1) / kFinishCellsPerBlock);
+    if (kmax_tpl == 8) {
+        hipLaunchKernelGGL((k_finish<D, 8, true>), dim3(nb_wave), dim3(kFinishThreads), 0, st, a);
+        hipLaunchKernelGGL((k_finish<D, 8, false>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_finish<D, 16, true>), dim3(nb_wave), dim3(kFinishThreads), 0, st, a);
+        hipLaunchKernelGGL((k_finish<D, 16, false>), dim3((unsigned)a.n_cells), dim3(kFinishThreads), 0, st, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
