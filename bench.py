@@ -465,6 +465,10 @@ def main():
         if len(judged):
             sv, sa, so = subset_gpu(v, alpha, data["cell_off"], judged, torch)
             comp_s = api.Compressor(len(judged), D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
+            if not args.no_tune:
+                # the refit batch gets its own launch plan, as the cold and
+                # warm batches do
+                tune["judged_fallback"] = comp_s.autotune(sv, sa, so)
             ms_extra = time_steps(lambda: comp_s(sv, sa, so), max(1, args.steps), 1, torch)
         ms = ms_warm + ms_extra
         em_ms, visits = ph_warm["em"], wr["visits"]
