@@ -30,6 +30,7 @@ STATUS = {
 MODE_STANDARD_EM = 1
 MODE_NO_FINISH = 2
 MODE_OUTER_K = 4
+MODE_ROUND32 = 8
 
 
 def build(force=False):
@@ -64,7 +65,7 @@ def _declare(L):
     L.orc_philox4x64_10.argtypes = [P, P, P]
     L.orc_philox4x64_10.restype = None
     L.orc_compress.argtypes = [P, P, P, I64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, F64, U64,
-                               ctypes.c_int, F64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+                               ctypes.c_int, F64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
     L.orc_compress.restype = ctypes.c_int
     L.orc_init_indices.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P]
     L.orc_init_indices.restype = None
@@ -157,7 +158,7 @@ def compress(v, alpha, cell_off, kmax, seed, D=None, n_min=10, max_sweeps=1000, 
         "mu": np.zeros((n_cells, kmax, D)), "sigma": np.zeros((n_cells, kmax, nt)),
         "moments": np.zeros((n_cells, 1 + D + nt)), "L_pen": np.zeros(n_cells), "L_final": np.zeros(n_cells),
         "sweeps": np.zeros(n_cells, np.int32), "status": np.zeros(n_cells, np.int32),
-        "visits": np.zeros(n_cells, np.int64),
+        "visits": np.zeros(n_cells, np.int64), "margin": np.zeros(n_cells),
     }
     fs = None if fixed_sweeps is None else _c(np.broadcast_to(fixed_sweeps, (n_cells,)), np.int32)
     Lt = Kt = None
@@ -174,7 +175,7 @@ def compress(v, alpha, cell_off, kmax, seed, D=None, n_min=10, max_sweeps=1000, 
                             float(T), _p(iK), _p(iw), _p(imu), _p(iS), _p(out["K"]), _p(out["omega"]),
                             _p(out["mu"]), _p(out["sigma"]), _p(out["moments"]), _p(out["L_pen"]),
                             _p(out["L_final"]), _p(out["sweeps"]), _p(out["status"]), _p(out["visits"]), _p(Lt),
-                            _p(Kt), nthreads or default_threads())
+                            _p(Kt), _p(out["margin"]), nthreads or default_threads())
     if rc != 0:
         raise ValueError("orc_compress rejected its arguments")
     if trace:

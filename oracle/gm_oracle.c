@@ -45,6 +45,11 @@
 #define ORC_MODE_NO_FINISH 2   /* report the penalised state, skip the unpenalised step */
 #define ORC_MODE_OUTER_K 4     /* outer search over K: after each converged run remove the
                                   least probable component and run again, keep the best */
+#define ORC_MODE_ROUND32 8     /* perturbation of the component-wise sweeps: each update's
+                                  responsibilities and the updated component's mean,
+                                  covariance and weight rounded to FP32 (binary32) before
+                                  use; sizes how far FP32 rounding alone moves a fit, for
+                                  the parity bars of FP32 iterations (test use only) */
 
 static const double LN_2PI = 1.8378770664093454835606594728112;
 static const double TWO_PI = 6.283185307179586476925286766559;
@@ -262,6 +267,8 @@ typedef struct {
     int64_t* visits;   /* component E/M updates performed */
     double* L_trace;   /* nullable: [n_cells * max_sweeps] penalised L after each sweep */
     int32_t* K_trace;  /* nullable: [n_cells * max_sweeps] live K after each sweep */
+    double* margin;    /* nullable: [n_cells] smallest |N_k - T/2| / (T/2) over the annihilation
+                          decisions of the sweeps (+inf when none was taken) */
 } compress_job;
 
 static int ntri(int D) { return D * (D + 1) / 2; }
@@ -493,6 +500,7 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
     }
     int64_t visits = 0;
     double L_s = 0.0;
+    double margin = INFINITY;
     int s = 0;
     for (int attempt = 0;; ++attempt) {
         if (have_init) {
@@ -546,6 +554,7 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
          * counts its own sweeps for the stop test and the cap. */
         const int standard = (J->mode & ORC_MODE_STANDARD_EM) != 0;
         const int outer = (J->mode & ORC_MODE_OUTER_K) != 0 && fixed <= 0 && !standard;
+        const int round32 = (J->mode & ORC_MODE_ROUND32) != 0;
         const int cap_sweeps = fixed > 0 ? fixed : J->max_sweeps;
         const double half_T = 0.5 * T;
         mixture best;
@@ -579,10 +588,13 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
                     while (k < m.K) {
                         /* step 1: E-step for component k with the current parameters */
                         responsibilities(D, &m, k, n, x, a, g);
+                        if (round32)
+                            for (int p = 0; p < n; ++p) g[p] = (double)(float)g[p];
                         double Nk = 0.0;
                         for (int p = 0; p < n; ++p) Nk += g[p];
                         ++visits;
                         if (fabs(Nk - half_T) < 1e-5 * half_T) status |= ORC_NEAR_TIE;
+                        if (half_T > 0.0 && fabs(Nk - half_T) / half_T < margin) margin = fabs(Nk - half_T) / half_T;
                         /* step 2: annihilate when N_k - T/2 <= 0 (eq. omegak) */
                         if (Nk - half_T <= 0.0) {
                             remove_component(&m, k);
@@ -593,6 +605,13 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
                         mean_cov(D, n, x, g, Nk, m.mu[k], m.S[k]);
                         /* eq. (omegak) with K the current number of live components */
                         m.w[k] = (Nk - half_T) / (N - half_T * m.K);
+                        if (round32) {
+                            m.w[k] = (double)(float)m.w[k];
+                            for (int i = 0; i < D; ++i) {
+                                m.mu[k][i] = (double)(float)m.mu[k][i];
+                                for (int j = 0; j < D; ++j) m.S[k][i][j] = (double)(float)m.S[k][i][j];
+                            }
+                        }
                         /* step 3: renormalise */
                         renormalise(&m);
                         if (factor_component(D, &m, k, trC)) status |= ORC_COV_FLOOR;
@@ -646,6 +665,7 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
     J->sweeps[c] = s;
     J->visits[c] = visits;
     J->L_pen[c] = L_s;
+    if (J->margin) J->margin[c] = margin;
 
     /* O7: one unpenalised joint step restores exact moments (Sec. 2.3.1) */
     if ((J->mode & ORC_MODE_NO_FINISH) == 0 && mle_finish(D, &m, n, x, a, N, g) != 0) {
@@ -726,12 +746,12 @@ int orc_compress(const double* v, const double* alpha, const int64_t* off, int64
                  double T_override, const int32_t* init_K, const double* init_w, const double* init_mu,
                  const double* init_S, int32_t* K, double* w, double* mu, double* S, double* mom, double* L_pen,
                  double* L_final, int32_t* sweeps, int32_t* status, int64_t* visits, double* L_trace,
-                 int32_t* K_trace, int nthreads)
+                 int32_t* K_trace, double* margin, int nthreads)
 {
     if (D < 1 || D > ORC_MAXD || kmax < 1 || kmax > ORC_MAXK || max_sweeps < 1) return -1;
     compress_job J = {v, alpha, off, n_cells, D, kmax, n_min, max_sweeps, fixed_sweeps, tol, seed, mode, T_override,
                       init_K, init_w, init_mu, init_S, K, w, mu, S, mom, L_pen, L_final, sweeps, status, visits,
-                      L_trace, K_trace};
+                      L_trace, K_trace, margin};
     run_chunks(n_cells, nthreads, compress_worker, &J, sizeof(compress_chunk), fill_compress);
     return 0;
 }

@@ -93,3 +93,14 @@ def deposit_at(x, w, off, dx, nx, cells):
                 tot += float((np.asarray(w[sl]) * s).sum())
         out.append(tot)
     return np.array(out)
+
+
+def take_cells(d, cells):
+    """The batch made of the given cells of d, in that order (renumbered)."""
+    off = d["cell_off"]
+    cells = np.asarray(cells)
+    counts = np.array([off[c + 1] - off[c] for c in cells], dtype=np.int64)
+    so = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    v = np.concatenate([d["v"][off[c]:off[c + 1]] for c in cells])
+    a = np.concatenate([d["alpha"][off[c]:off[c + 1]] for c in cells])
+    return dict(v=v, alpha=a, cell_off=so)

@@ -9,7 +9,7 @@ import oracle
 from paper_2007_12273_amd import synth
 
 from gpu_util import dev, host, to_gpu, torch
-from test_gpu_compress import _check_record
+import fp32_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_every_variant_matches_oracle_replay(D, kmax):
     v, a, off = to_gpu(d)
     o = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=kmax, seed=9, max_sweeps=20)
     fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
+    res = fp32_parity.resolution(d, kmax, 9, o["sweeps"], o)
     default = (MAXN8 if kmax <= 8 else MAXN16)
     try:
         for var in VARIANTS:
@@ -60,8 +61,7 @@ def test_every_variant_matches_oracle_replay(D, kmax):
             api.autotune_set(D, kmax, fill)
             g = host(api.compress(v, a, off, kmax, seed=9, fixed_sweeps=fs, max_sweeps=20))
             assert np.array_equal(g["sweeps"], o["sweeps"])
-            _check_record(g, o, D, k_frac=0.9, par_frac=0.85, par_max=1e-2,
-                          label="D %d variant %s kmax %d" % (D, var, kmax), n=np.diff(d["cell_off"]))
+            fp32_parity.check(g, o, d, res, "D %d variant %s kmax %d" % (D, var, kmax))
     finally:
         api.autotune_reset()
 
@@ -87,7 +87,7 @@ def test_autotune_installs_a_working_plan():
         o = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=16, seed=2003, max_sweeps=60)
         fs = torch.from_numpy(o["sweeps"].astype(np.int32)).to(dev())
         g = host(comp(v, a, offg, fixed_sweeps=fs).as_dict())
-        _check_record(g, o, 3, k_frac=0.95, par_frac=0.9, par_max=1e-2, label="tuned plan replay",
-                      n=np.diff(sub["cell_off"]))
+        res = fp32_parity.resolution(sub, 16, 2003, o["sweeps"], o)
+        fp32_parity.check(g, o, sub, res, "tuned plan replay")
     finally:
         api.autotune_reset()

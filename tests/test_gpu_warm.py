@@ -19,7 +19,8 @@ import oracle
 from paper_2007_12273_amd import synth
 
 from gpu_util import dev, host, to_gpu, torch
-from test_gpu_compress import _check_record, _subset
+import fp32_parity
+from test_gpu_compress import _subset
 
 pytestmark = pytest.mark.gpu
 
@@ -319,8 +320,8 @@ def test_pipeline_warm_compress_matches_oracle():
                          fixed_sweeps=np.where(keep, o["sweeps"], 1))
     g2 = host(api.compress(v, a, off, 16, seed=4, max_sweeps=150, init=gi, fixed_sweeps=fs))
     np.testing.assert_array_equal(g2["sweeps"], o2["sweeps"])
-    _check_record(g2, o2, 3, cells=list(np.nonzero(keep)[0]), k_frac=0.95, par_frac=0.9, par_max=1e-2,
-                  label="pipeline replay", n=np.diff(d["cell_off"]))
+    res = fp32_parity.resolution(d, 16, 4, o2["sweeps"], o2, init=init)
+    fp32_parity.check(g2, o2, d, res, "pipeline replay", cells=list(np.nonzero(keep)[0]))
     m.close()
 
 
@@ -332,7 +333,9 @@ def test_warm_fallback_matches_oracle():
     assert ((o["status"] & FALLBACK) != 0).all()
     np.testing.assert_array_equal(g["status"] & FALLBACK, o["status"] & FALLBACK)
     np.testing.assert_array_equal(g["sweeps"], o["sweeps"])
-    _check_record(g, o, 3, k_frac=0.9, par_frac=0.9, par_max=2e-3, label="fallback", n=np.diff(d["cell_off"]))
+    # every cell fell back: its record is the cold fit's
+    res = fp32_parity.resolution(d, 16, 5, o["sweeps"], o)
+    fp32_parity.check(g, o, d, res, "fallback")
     # a start at the generating Gaussian is kept
     iu = np.triu_indices(3)
     good = {"K": np.ones(12, np.int32), "omega": np.zeros((12, 16)), "mu": np.zeros((12, 16, 3)),

@@ -522,3 +522,32 @@ def test_outer_k_search_on_single_gaussian_cells(kmax):
     assert worse.any() and (outer["K"][worse] == 1).all()
     # one more run, of at least two sweeps, per removed component
     assert (outer["sweeps"] >= plain["sweeps"] + 2 * (plain["K"] - 1)).all()
+
+
+@pytest.mark.parametrize("name", ["weibel_3v", "mix_1v"])
+def test_likelihood_shifts_with_the_velocity_unit(name):
+    """Scaling every velocity by s (a change of unit) maps the fit to the
+    scaled fit -- same decisions, means times s, covariances times s^2 --
+    and lowers eq. (lnL-GM) by N D ln s exactly: each density f(v) becomes
+    f(v / s) / s^D and the weights sum to N, while the penalty does not
+    depend on the unit.  A dropped log-determinant or normalisation term
+    breaks the shift.  It also means |L| has no unit-free size (a suitable s
+    puts L at zero), which is why the GPU parity bars take likelihood errors
+    relative to max(|L|, N)."""
+    d = synth.make(name)
+    off = d["cell_off"]
+    nc = 12
+    v, a, co = d["v"][:off[nc]], d["alpha"][:off[nc]], off[:nc + 1]
+    D = d["D"]
+    s = 3.7
+    r1 = oracle.compress(v, a, co, kmax=d["kmax"], seed=5, fixed_sweeps=25)
+    r2 = oracle.compress(v * s, a, co, kmax=d["kmax"], seed=5, fixed_sweeps=25)
+    n = np.diff(co).astype(float)
+    np.testing.assert_array_equal(r1["K"], r2["K"])
+    np.testing.assert_array_equal(r1["visits"], r2["visits"])
+    for key in ("L_pen", "L_final"):
+        shifted = r1[key] - n * D * np.log(s)
+        np.testing.assert_allclose(r2[key], shifted, rtol=0, atol=1e-9 * np.abs(r1[key]).max() + 1e-9 * n.max())
+    np.testing.assert_allclose(r2["omega"], r1["omega"], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(r2["mu"], s * r1["mu"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r2["sigma"], s * s * r1["sigma"], rtol=1e-9, atol=1e-14)
