@@ -53,6 +53,7 @@ extern "C" {
 #define GM_ENOTIMPL (-4)  /* combination not built into this library */
 #define GM_ENOCONV (-5)   /* iterative solve stopped above its tolerance */
 #define GM_EIO (-6)       /* a file could not be opened, read or written */
+#define GM_ETOOBIG (-7)   /* input larger than a fixed limit of the entry point */
 
 /* ---- per-cell status bits ---- */
 #define GM_ST_SMALL_CELL_K1 (1 << 0)   /* n <= n_min: single Gaussian with the cell's moments */
@@ -149,6 +150,27 @@ size_t gm_compress_workspace(int64_t n_cells, const gm_opts* o);
 int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
                 const gm_opts* o, const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out,
                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gm_compress_noalloc -- gm_compress for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * gm_compress, without the workspace: the library keeps the workspace in a
+ * fixed device array of its own, one per GPU, held until the process ends
+ * (about 11 MB: n_cells <= GM_NOALLOC_MAX_CELLS; larger batches return
+ * GM_ETOOBIG and enqueue nothing).  The first call on a device looks up that
+ * device's array and creates the library's stream set for it (no memory
+ * allocation); later calls only enqueue kernels.  The array starts every call
+ * from kernels that rewrite what they read, so a call does not depend on the
+ * previous one.  Calls that overlap on one GPU (two host threads, or two
+ * streams without ordering between them) share the array and race: order
+ * them on one stream or serialise them.  Callers that can allocate should
+ * use gm_compress with their own workspace.
+ */
+#define GM_NOALLOC_MAX_CELLS 65536
+int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                        const gm_opts* o, const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out,
+                        void* stream);
 
 /* ---- launch-plan autotuner ----
  * gm_compress runs the EM iterations in twelve length buckets (bucket b

@@ -11,7 +11,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmcr.so")
 
-GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL, GM_ENOCONV, GM_EIO = 0, -1, -2, -3, -4, -5, -6
+GM_OK, GM_EINVAL, GM_EHIP, GM_ENOMEM, GM_ENOTIMPL, GM_ENOCONV, GM_EIO, GM_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+GM_NOALLOC_MAX_CELLS = 65536
 GM_TUNE_REPORT_LEN = 38
 
 STATUS = {
@@ -40,7 +41,7 @@ class GmInit(ctypes.Structure):
     _fields_ = [(n, P) for n in ("K", "omega", "mu", "sigma")]
 
 
-EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
+EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_compress_noalloc", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
@@ -71,6 +72,9 @@ def load():
     L.gm_compress.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmInit),
                               ctypes.POINTER(GmMix), P, ctypes.c_size_t, P]
     L.gm_compress.restype = ctypes.c_int
+    L.gm_compress_noalloc.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmInit),
+                                      ctypes.POINTER(GmMix), P]
+    L.gm_compress_noalloc.restype = ctypes.c_int
     L.gm_autotune.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), ctypes.POINTER(GmInit),
                               ctypes.POINTER(GmMix), P, ctypes.c_size_t, P, P, ctypes.c_int32]
     L.gm_autotune.restype = ctypes.c_int

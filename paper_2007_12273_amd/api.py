@@ -190,6 +190,38 @@ def compress(v, alpha, cell_off, kmax, n_min=10, max_sweeps=1000, tol=1e-7, seed
     return c(v.contiguous(), alpha, cell_off, fixed_sweeps=fixed_sweeps, init=init, stream=stream).as_dict()
 
 
+def compress_noalloc(v, alpha, cell_off, out, opts, fixed_sweeps=None, init=None, stream=None):
+    """gm_compress_noalloc: the compress of `compress` into the caller's
+    MixtureBuffers `out` with the library's fixed scratch instead of a
+    workspace (at most GM_NOALLOC_MAX_CELLS cells).  `opts` from make_opts.
+    Allocates nothing on the device."""
+    _need(v, torch.float64, "v")
+    _need(alpha, torch.float64, "alpha")
+    _need(cell_off, torch.int64, "cell_off")
+    n_cells = cell_off.numel() - 1
+    if n_cells != out.n_cells or out.D != opts.D or out.kmax != opts.kmax:
+        raise ValueError("output buffers do not match the batch and options")
+    if v.numel() != alpha.numel() * opts.D:
+        raise ValueError("v must be [n, D] with n = len(alpha)")
+    fs = None
+    if fixed_sweeps is not None:
+        _need(fixed_sweeps, torch.int32, "fixed_sweeps")
+        fs = _ptr(fixed_sweeps)
+    ini = None
+    if init is not None:
+        ini = GmInit()
+        for name in ("K", "omega", "mu", "sigma"):
+            t = init[name]
+            _need(t, torch.int32 if name == "K" else torch.float64, "init." + name)
+            setattr(ini, name, t.data_ptr())
+        ini = ctypes.byref(ini)
+    mix = out.struct()
+    rc = _lib.load().gm_compress_noalloc(_ptr(v), _ptr(alpha), _ptr(cell_off), n_cells, ctypes.byref(opts), fs, ini,
+                                         ctypes.byref(mix), _stream(stream))
+    check(rc, "gm_compress_noalloc")
+    return out
+
+
 class Reconstructor:
     """Reusable reconstruct call: owns the output particle arrays."""
 

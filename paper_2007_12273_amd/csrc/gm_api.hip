@@ -5,6 +5,7 @@
 #include "gm_compress_impl.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace gm {
 int launch_compress_d1_float(int, int, int, int, const CompressArgs&, int, hipStream_t);
@@ -27,7 +28,7 @@ int launch_std_d3(const StdArgs&, int64_t, hipStream_t);
 
 namespace {
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // phase timing: events recorded on the caller's stream around the compress
 // phases (plan, EM, finish) and the reconstruct launch
@@ -195,33 +196,10 @@ bool valid_opts(const gm_opts* o)
     return true;
 }
 
-}  // namespace
-
-extern "C" {
-
-void gm_opts_default(gm_opts* o, int32_t D, int32_t kmax)
-{
-    if (!o) return;
-    memset(o, 0, sizeof(*o));
-    o->D = D;
-    o->kmax = kmax;
-    o->n_min = 10;
-    o->max_sweeps = 1000;
-    o->tol_rel = 1e-7;
-    o->seed = 0;
-    o->estep_fp64 = 0;
-    o->outer_k = 0;
-}
-
-size_t gm_compress_workspace(int64_t n_cells, const gm_opts* o)
-{
-    if (!o || n_cells < 0) return 0;
-    return ws_layout(n_cells, o->D).total;
-}
-
-int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,
-                const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,
-                void* stream)
+// ---- compress: argument checks and the launch sequence shared by
+// gm_compress (caller workspace) and gm_compress_noalloc (fixed scratch) ----
+int compress_check(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,
+                   const gm_init* init, const gm_mix* out)
 {
     if (!valid_opts(o) || n_cells < 0 || n_cells > 0x7fffffff || !out) return GM_EINVAL;
     if (n_cells == 0) return GM_OK;
@@ -230,11 +208,13 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
         !out->sweeps || !out->status || !out->visits)
         return GM_EINVAL;
     if (init && init->K && (!init->omega || !init->mu || !init->sigma)) return GM_EINVAL;
-    const WsLayout L = ws_layout(n_cells, o->D);
-    if (!ws || ws_bytes < L.total) return GM_ENOMEM;
-    hipStream_t st = (hipStream_t)stream;
-    char* w = (char*)ws;
+    return GM_OK;
+}
 
+int compress_run(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,
+                 const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out, char* w, hipStream_t st)
+{
+    const WsLayout L = ws_layout(n_cells, o->D);
     gm::CompressArgs a;
     memset(&a, 0, sizeof(a));
     a.v = v;
@@ -274,6 +254,82 @@ int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, i
     rc = D == 1 ? gm::launch_compress_finish_d1(kt, a, st) : gm::launch_compress_finish_d3(kt, a, st);
     prof_mark(EV_END, st);
     return rc ? GM_EHIP : GM_OK;
+}
+
+// ---- fixed scratch of gm_compress_noalloc ----
+// The workspace of up to GM_NOALLOC_MAX_CELLS cells (the larger of the 1V
+// and 3V layouts), one copy per device for the life of the process.  Host
+// code never uses the array's name as an address: the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes =
+    align256(gm::PLAN_SIZE * sizeof(int32_t)) + align256((size_t)GM_NOALLOC_MAX_CELLS * sizeof(gm::CellInfo<3>)) +
+    align256((size_t)GM_NOALLOC_MAX_CELLS * sizeof(int32_t)) +
+    align256((size_t)GM_NOALLOC_MAX_CELLS * gm::kInitSlots * sizeof(int32_t));
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+char* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// device address of this device's scratch (and its library streams), set
+// up on the first call on the device; nullptr on a HIP error
+char* scratch_for_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        if (!fork_for_device()) return nullptr;
+        g_scratch[dev] = static_cast<char*>(p);
+    }
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+void gm_opts_default(gm_opts* o, int32_t D, int32_t kmax)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->D = D;
+    o->kmax = kmax;
+    o->n_min = 10;
+    o->max_sweeps = 1000;
+    o->tol_rel = 1e-7;
+    o->seed = 0;
+    o->estep_fp64 = 0;
+    o->outer_k = 0;
+}
+
+size_t gm_compress_workspace(int64_t n_cells, const gm_opts* o)
+{
+    if (!o || n_cells < 0) return 0;
+    return ws_layout(n_cells, o->D).total;
+}
+
+int gm_compress(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells, const gm_opts* o,
+                const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,
+                void* stream)
+{
+    const int rc = compress_check(v, alpha, cell_off, n_cells, o, init, out);
+    if (rc != GM_OK || n_cells == 0) return rc;
+    if (!ws || ws_bytes < ws_layout(n_cells, o->D).total) return GM_ENOMEM;
+    return compress_run(v, alpha, cell_off, n_cells, o, fixed_sweeps, init, out, (char*)ws, (hipStream_t)stream);
+}
+
+int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                        const gm_opts* o, const int32_t* fixed_sweeps, const gm_init* init, const gm_mix* out,
+                        void* stream)
+{
+    const int rc = compress_check(v, alpha, cell_off, n_cells, o, init, out);
+    if (rc != GM_OK || n_cells == 0) return rc;
+    if (n_cells > GM_NOALLOC_MAX_CELLS) return GM_ETOOBIG;
+    char* w = scratch_for_device();
+    if (!w) return GM_EHIP;
+    return compress_run(v, alpha, cell_off, n_cells, o, fixed_sweeps, init, out, w, (hipStream_t)stream);
 }
 
 size_t gm_compress_standard_workspace(int64_t n_cells, int64_t n_tot, const gm_opts* o)
@@ -691,6 +747,7 @@ const char* gm_strerror(int code)
         case GM_ENOTIMPL: return "not implemented in this build";
         case GM_ENOCONV: return "iterative solve did not reach its tolerance";
         case GM_EIO: return "file could not be opened, read or written";
+        case GM_ETOOBIG: return "input larger than the fixed scratch of the allocation-free entry point";
         default: return "unknown error";
     }
 }
