@@ -19,7 +19,11 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libgmoracle.so")
+# GM_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload the ASan runtime;
+# tests/test_oracle_sanitizers.py runs it in a subprocess)
+_SANITIZE = os.environ.get("GM_ORACLE_SANITIZE") == "1"
+_SO = os.path.join(_HERE, "libgmoracle_san.so" if _SANITIZE else "libgmoracle.so")
 _SRC = [os.path.join(_HERE, f) for f in ("gm_oracle.c", "gm_oracle_mlp.c") if os.path.exists(os.path.join(_HERE, f))]
 
 STATUS = {
@@ -38,8 +42,10 @@ def build(force=False):
     if not force and os.path.exists(_SO) and all(os.path.getmtime(_SO) >= os.path.getmtime(s) for s in _SRC):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
-           "-o", tmp] + _SRC + ["-lm", "-lpthread"]
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"] \
+        if _SANITIZE else ["-O2"]
+    cmd = ["gcc"] + opt + ["-std=gnu11", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+                           "-o", tmp] + _SRC + ["-lm", "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, _SO)
     return _SO
