@@ -175,8 +175,13 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
 /* ---- launch-plan autotuner ----
  * gm_compress runs the EM iterations in twelve length buckets (bucket b
  * holds the cells of up to 64 * 2^b particles, refined at kmax 16), each a
- * persistent launch whose workgroups take cells from a queue, spread over
- * the caller's stream and three library streams.  A bucket can run with
+ * persistent launch whose workgroups take cells from a queue, each on a
+ * stream of its own (eleven library streams and the caller's), so that all
+ * twelve run concurrently.  HIP maps streams onto GPU_MAX_HW_QUEUES hardware
+ * queues per process (default 4): run with GPU_MAX_HW_QUEUES >= 12 (set
+ * before the HIP runtime starts) for the buckets to overlap; with fewer,
+ * launches sharing a queue run one after another (same results, longer EM
+ * phase).  A bucket can run with
  * several launch variants: particles per thread (1, 2, 4, 8, 16), the
  * matching number of 64-lane waves per workgroup, density terms kept in
  * registers or recomputed, and the standard build (up to 8 waves per
@@ -196,8 +201,8 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * the built-in plan (ms), [1] of the tuned plan, [2 + b] bucket b's
  * fastest standalone time (0 when empty), [14 + b] the installed variant of
  * bucket b as per_thread * 1000 + waves * 10 + mode, mode = (1 if
- * register-resident) + (2 if lean), [26 + b] its stream (0-2 library
- * streams, 3 the caller's). */
+ * register-resident) + (2 if lean), [26 + b] its stream (0-10 library
+ * streams, 11 the caller's). */
 #define GM_TUNE_REPORT_LEN 38
 int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
                 const gm_opts* o, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,

@@ -55,16 +55,13 @@ struct WsLayout {
     size_t plan, cells, list, init, total;
 };
 
-// auxiliary streams for concurrent length buckets, one set per device
-constexpr int kLanes = 4;
-// bucket -> lane (0..2 auxiliary, 3 the caller's stream).  Each bucket's
-// makespan is set by its slowest cell, so the mapping spreads the buckets
-// that measured longest on the 1D3V Weibel-like workload over different
-// lanes (the 257-512 bucket holds small cells that keep 16 components for
-// the whole sweep cap; the two recompute-mode buckets hold the largest
-// cells); buckets are launched largest first on every lane.
-constexpr int kBucketLane16[gm::kNumBuckets] = {0, 0, 0, 0, 3, 3, 1, 2, 3, 3, 1, 2};
-constexpr int kBucketLane8[gm::kNumBuckets] = {0, 1, 2, 3, 0, 1, 2, 3, 0, 1, 2, 3};
+// Streams of the EM phase, one set per device: every length bucket runs on
+// a stream of its own (the caller's stream carries the last one), so the
+// twelve bucket launches can run concurrently.  HIP maps streams onto
+// GPU_MAX_HW_QUEUES hardware queues (default 4); the buckets only all run at
+// once with at least twelve.  With fewer, streams share queues round-robin
+// and the launches sharing a queue run one after another.
+constexpr int kLanes = gm::kNumBuckets;
 struct Fork {
     hipStream_t aux[kLanes - 1];
     hipEvent_t fork;
@@ -102,6 +99,9 @@ struct EmPlan {
     bool tuned;
 };
 
+// bucket b on stream b (the largest cells' bucket on the caller's stream)
+constexpr int kNumLaneOf(int b) { return b; }
+
 EmPlan default_plan(int kt)
 {
     EmPlan p;
@@ -110,7 +110,7 @@ EmPlan default_plan(int kt)
         p.per_thread[b] = (int8_t)c.per_thread;
         p.mode[b] = (int8_t)(c.store_e ? gm::kModeStoreE : 0);
         p.waves[b] = (int8_t)c.waves;
-        p.lane[b] = (int8_t)(kt == 8 ? kBucketLane8[b] : kBucketLane16[b]);
+        p.lane[b] = (int8_t)(kNumLaneOf(b));
         p.order[b] = (int8_t)(gm::kNumBuckets - 1 - b);  // largest cells first
     }
     p.tuned = false;
@@ -156,7 +156,9 @@ int launch_em_phase(int D, bool fp64, int kt, const EmPlan& p, gm::CompressArgs&
 {
     Fork* fk = fork_for_device();
     if (!fk) return -1;
-    hipStream_t lanes[kLanes] = {fk->aux[0], fk->aux[1], fk->aux[2], st};
+    hipStream_t lanes[kLanes];
+    for (int i = 0; i < kLanes - 1; ++i) lanes[i] = fk->aux[i];
+    lanes[kLanes - 1] = st;
     if (hipEventRecord(fk->fork, st) != hipSuccess) return -1;
     for (int i = 0; i < kLanes - 1; ++i)
         if (hipStreamWaitEvent(fk->aux[i], fk->fork, 0) != hipSuccess) return -1;
@@ -509,8 +511,9 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
         }
     }
     // A tuned plan from a choice of candidate per bucket: buckets spread
-    // over the lanes longest first onto the least-loaded lane, and launched
-    // in that order.  Two choices: the fastest variant alone, and the
+    // over the streams longest first onto the least-loaded one (with a
+    // stream per bucket, each bucket gets its own), and launched in that
+    // order.  Two choices: the fastest variant alone, and the
     // fastest lean-build variant where the bucket has one.  Alone, a bucket
     // has the device to itself; in the concurrent phase the lean builds
     // leave room on a CU for the other buckets' workgroups, which can beat
@@ -528,7 +531,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
             }
         }
         std::stable_sort(idx, idx + gm::kNumBuckets, [&](int x, int y) { return ms[x] > ms[y]; });
-        double load[kLanes] = {0, 0, 0, 0};
+        double load[kLanes] = {};
         for (int i = 0; i < gm::kNumBuckets; ++i) {
             const int b = idx[i];
             int l = 0;

@@ -16,16 +16,33 @@ import torch
 from . import api
 
 
-def training_set(batches, kmax, seed=0, device="cuda"):
+def best_fit(v, a, off, kmax, seeds):
+    """Plain-EM fit of every cell from each cold-start seed in `seeds`; per
+    cell the fit with the highest penalised likelihood is kept."""
+    best = None
+    for s in seeds:
+        r = api.compress(v, a, off, kmax, seed=s)
+        if best is None:
+            best = r
+            continue
+        better = r["L_pen"] > best["L_pen"]
+        for k in best:
+            m = better.view(-1, *([1] * (best[k].dim() - 1)))
+            best[k] = torch.where(m, r[k], best[k])
+    return best
+
+
+def training_set(batches, kmax, seed=0, device="cuda", restarts=1):
     """Features [N, 128] and targets [N, 160] (device tensors) of every cell
     in `batches`, a list of {v, alpha, cell_off} host arrays; the targets
-    are the plain-EM fits of the cells."""
+    are the plain-EM fits of the cells (the best of `restarts` cold starts,
+    seeds seed, seed + 1, ...)."""
     feats, targs = [], []
     for b in batches:
         v = torch.from_numpy(b["v"]).to(device)
         a = torch.from_numpy(b["alpha"]).to(device)
         off = torch.from_numpy(b["cell_off"]).to(device)
-        r = api.compress(v, a, off, kmax, seed=seed)
+        r = best_fit(v, a, off, kmax, [seed + i for i in range(restarts)])
         f, fr = api.warm_features(v, a, off)
         feats.append(f)
         targs.append(api.warm_targets(r, fr))

@@ -79,7 +79,7 @@ def test_autotune_installs_a_working_plan():
         print("autotune:", rep)
         assert rep["builtin_em_ms"] > 0 and rep["tuned_em_ms"] > 0
         for code, lane in zip(rep["variant"], rep["lane"]):
-            assert code // 1000 in (1, 2, 4, 8, 16) and code % 10 <= 3 and 0 <= lane <= 3
+            assert code // 1000 in (1, 2, 4, 8, 16) and code % 10 <= 3 and 0 <= lane <= 11
         tuned = host(comp.out.as_dict())
         again = host(comp(v, a, offg).as_dict())
         for k in ("K", "sweeps", "status"):
