@@ -575,8 +575,15 @@ __device__ __forceinline__ double sqrt_det(const double* C)
 // threads compute the identical M-step, so a wave can publish an update to
 // its copy without waiting for the others.  The only workgroup barrier per
 // component update is the one inside the cross-wave reduction.
+// Standard FP32 builds are held to three waves per SIMD (at most 168 VGPRs)
+// so that a CU holds two cells of up to five waves each; the FP64 builds keep
+// the whole register file (two waves per SIMD).
+template <typename R, bool LEAN>
+constexpr int em_min_waves_per_simd() { return (LEAN || !std::is_same<R, float>::value) ? 1 : 3; }
+
 template <int D, int KMAX, int P, bool STORE_E, typename R, bool LEAN>
-__global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads) void k_em(CompressArgs A_in)
+__global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_waves_per_simd<R, LEAN>())) void k_em(
+    CompressArgs A_in)
 {
     constexpr int MAXW = em_max_waves(LEAN);
     constexpr int NT = ntri(D);
