@@ -43,9 +43,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
-# hardware queues for the twelve concurrent length-bucket launches of the EM
+# hardware queues for the thirteen concurrent launches of the EM
 # phase (HIP's default is 4); read when the HIP runtime starts
-if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 12:
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 13:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "particles fit/s, batched GM-EM 1D3V: learned warm-start vs plain EM"
@@ -410,7 +410,6 @@ def main():
     D, kmax, dx = W["D"], W["kmax"], W["dx"]
 
     comp_c = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
-    comp_w = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
     recon = api.Reconstructor(off, D, dx, device=dev)
 
     model = None
@@ -437,9 +436,13 @@ def main():
         r = comp_c(v, alpha, off)
         recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
+    if warm:
+        # the whole warm start and the compress in one library call
+        # (gm_compress_warm: features, network, decode, EM, finish)
+        comp_w = api.WarmCompressor(n_cells, model, device=dev, seed=W["init_seed"])
+
     def warm_step():
-        init = model.initial_mixtures(v, alpha, off, bufs=bufs)
-        r = comp_w(v, alpha, off, init=init)
+        r = comp_w(v, alpha, off)
         recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
     tune = {}
@@ -473,12 +476,15 @@ def main():
         ms_warm = time_steps(warm_step, args.steps, args.warmup, torch)
         log("warm: %.3f ms/step" % ms_warm)
 
+        comp_wp = api.Compressor(n_cells, D, kmax, device=dev, seed=W["init_seed"], fp64=fp64)
+
         def warm_step_timed():
+            # the same step as separate calls, for the phase breakdown
             s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             s0.record()
             init = model.initial_mixtures(v, alpha, off, bufs=bufs)
             s1.record()
-            r = comp_w(v, alpha, off, init=init)
+            r = comp_wp(v, alpha, off, init=init)
             recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
             torch.cuda.synchronize()
             return s0.elapsed_time(s1)

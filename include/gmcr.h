@@ -31,9 +31,10 @@
  *   - Mixture records are padded to kmax components; slots >= K hold zeros.
  *   - Covariances are stored as the packed upper triangle, row-major:
  *     D = 3 -> (xx, xy, xz, yy, yz, zz); D = 1 -> (xx).
- *   - Limits: D in {1, 3}; 1 <= kmax <= 16; at most 8192 particles per
- *     cell (larger cells get K = 0 and GM_ST_DEGENERATE); reconstruct
- *     position dimensions 0 <= dx <= 3.
+ *   - Limits: D in {1, 3}; 1 <= kmax <= 16; reconstruct position
+ *     dimensions 0 <= dx <= 3.  Cells of up to 8192 particles run in the
+ *     register-resident EM launches; larger cells in a launch that re-reads
+ *     their particles on every pass (same results, slower per particle).
  */
 #ifndef GMCR_H
 #define GMCR_H
@@ -109,9 +110,12 @@ typedef struct gm_mix {
 
 /* Optional initial mixtures (learned warm start).  Cells with K[c] > 0
  * start from them instead of the random cold start; mu in the same
- * coordinates as v.  Same layout as gm_mix; K[c] <= kmax, and the caller
- * keeps n w_k > T/2 for every supplied component (gm_warm_decode does).
- * When running to convergence, a cell whose warm-started penalised
+ * coordinates as v.  Same layout as gm_mix; the first min(K[c], kmax) slots
+ * are used, their weights renormalised.  A start for which eq. (omegak) is
+ * undefined -- N - T K / 2 <= 0, or N w_k <= T/2 for a supplied component
+ * (N the cell's particle count, T = D(D+3)/2) -- is not used: the cell
+ * starts cold and is flagged GM_ST_WARM_FALLBACK (gm_warm_decode never
+ * produces one).  When running to convergence, a cell whose warm-started penalised
  * likelihood ends below that of the single Gaussian with its moments, less
  * 1e-5 of its magnitude, is fitted again from the cold start and flagged
  * GM_ST_WARM_FALLBACK (its other flags are the cold fit's; visits count
@@ -176,12 +180,12 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * gm_compress runs the EM iterations in twelve length buckets (bucket b
  * holds the cells of up to 64 * 2^b particles, refined at kmax 16), each a
  * persistent launch whose workgroups take cells from a queue, each on a
- * stream of its own (eleven library streams and the caller's), so that all
- * twelve run concurrently.  HIP maps streams onto GPU_MAX_HW_QUEUES hardware
- * queues per process (default 4): run with GPU_MAX_HW_QUEUES >= 12 (set
- * before the HIP runtime starts) for the buckets to overlap; with fewer,
- * launches sharing a queue run one after another (same results, longer EM
- * phase).  A bucket can run with
+ * library stream of its own (cells of more than 8192 particles run on the
+ * caller's stream), so that all thirteen launches run concurrently.  HIP
+ * maps streams onto GPU_MAX_HW_QUEUES hardware queues per process (default
+ * 4): run with GPU_MAX_HW_QUEUES >= 13 (set before the HIP runtime starts)
+ * for them to overlap; with fewer, launches sharing a queue run one after
+ * another (same results, longer EM phase).  A bucket can run with
  * several launch variants: particles per thread (1, 2, 4, 8, 16), the
  * matching number of 64-lane waves per workgroup, density terms kept in
  * registers or recomputed, and the standard build (up to 8 waves per
@@ -201,8 +205,9 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * the built-in plan (ms), [1] of the tuned plan, [2 + b] bucket b's
  * fastest standalone time (0 when empty), [14 + b] the installed variant of
  * bucket b as per_thread * 1000 + waves * 10 + mode, mode = (1 if
- * register-resident) + (2 if lean), [26 + b] its stream (0-10 library
- * streams, 11 the caller's). */
+ * register-resident) + (2 if lean), [26 + b] its stream (0-11 library
+ * streams, 12 the caller's, which also carries the cells larger than the
+ * buckets hold). */
 #define GM_TUNE_REPORT_LEN 38
 int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
                 const gm_opts* o, const gm_init* init, const gm_mix* out, void* ws, size_t ws_bytes,
@@ -383,6 +388,29 @@ int gm_warm_forward(const gm_warm* model, const uint16_t* feats, int64_t n_rows,
  * the frame has no factor).  cell_off gives the cell sizes n. */
 int gm_warm_decode(const float* Y, const double* frame, const int64_t* cell_off, int64_t n_cells, int32_t kmax,
                    int32_t* K, double* omega, double* mu, double* sigma, void* stream);
+
+/* kmax of a model (the number of component slots it predicts); 0 for NULL. */
+int gm_warm_model_kmax(const gm_warm* model);
+
+/*
+ * gm_compress_warm -- the learned warm start and the compress in one call
+ * (the warm path of the compress entry point: gm_compress with a model
+ * handle).  Enqueues on `stream`: features of every cell (gm_warm_features),
+ * the network (gm_warm_forward), decode into initial mixtures
+ * (gm_warm_decode), then gm_compress from those mixtures (converged mode;
+ * a cell whose warm fit ends below the single Gaussian is refitted from the
+ * cold start and flagged GM_ST_WARM_FALLBACK, see gm_init).  The result is
+ * the one gm_compress gives for the decoded mixtures.  Arguments as for
+ * gm_compress; o->D must be 3 and o->kmax the model's kmax (GM_EINVAL
+ * otherwise).  ws: device workspace of at least
+ * gm_compress_warm_workspace(n_cells, o) bytes holding the compress
+ * workspace, the features, frames, network outputs and decoded mixtures.
+ * The model is only read (its weights); calls on one model may overlap.
+ */
+size_t gm_compress_warm_workspace(int64_t n_cells, const gm_opts* o);
+int gm_compress_warm(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                     const gm_opts* o, const gm_warm* model, const gm_mix* out, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* Training targets [n_cells * 160] FP32 from fitted mixtures (gm_mix
  * layout, kmax slots) and frames.  A component whose whitened covariance

@@ -498,6 +498,21 @@ static void compress_cell(const compress_job* J, int64_t c, double* x, double* a
         memcpy(one.L[0], LC, sizeof(LC));
         L_one = penalised_L(D, T, &one, n, x, a, N);
     }
+    /* A supplied start is used only where eq. (omegak) is defined for it:
+     * N - T K / 2 > 0 and N w_k > T/2 for every supplied component (weights
+     * renormalised over the K used); otherwise the cell starts cold and is
+     * flagged as a rejected warm start. */
+    if (have_init) {
+        int K0 = J->init_K[c] < J->kmax ? J->init_K[c] : J->kmax;
+        double ws = 0.0;
+        for (int k = 0; k < K0; ++k) ws += J->init_w[(size_t)c * J->kmax + k];
+        int usable = N - 0.5 * T * K0 > 0.0 && ws > 0.0 && isfinite(ws);
+        for (int k = 0; k < K0; ++k) usable &= N * (J->init_w[(size_t)c * J->kmax + k] / ws) > 0.5 * T;
+        if (!usable) {
+            have_init = 0;
+            status = ORC_WARM_FALLBACK;
+        }
+    }
     int64_t visits = 0;
     double L_s = 0.0;
     double margin = INFINITY;

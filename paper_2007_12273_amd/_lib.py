@@ -41,7 +41,8 @@ class GmInit(ctypes.Structure):
     _fields_ = [(n, P) for n in ("K", "omega", "mu", "sigma")]
 
 
-EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_compress_noalloc", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
+EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_compress_noalloc", "gm_compress_warm",
+           "gm_compress_warm_workspace", "gm_warm_model_kmax", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
@@ -75,6 +76,13 @@ def load():
     L.gm_compress_noalloc.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmInit),
                                       ctypes.POINTER(GmMix), P]
     L.gm_compress_noalloc.restype = ctypes.c_int
+    L.gm_compress_warm_workspace.argtypes = [ctypes.c_int64, ctypes.POINTER(GmOpts)]
+    L.gm_compress_warm_workspace.restype = ctypes.c_size_t
+    L.gm_compress_warm.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmMix), P,
+                                   ctypes.c_size_t, P]
+    L.gm_compress_warm.restype = ctypes.c_int
+    L.gm_warm_model_kmax.argtypes = [P]
+    L.gm_warm_model_kmax.restype = ctypes.c_int
     L.gm_autotune.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), ctypes.POINTER(GmInit),
                               ctypes.POINTER(GmMix), P, ctypes.c_size_t, P, P, ctypes.c_int32]
     L.gm_autotune.restype = ctypes.c_int

@@ -144,6 +144,37 @@ class Compressor:
                 "variant": [int(x) for x in r[2 + nb:2 + 2 * nb]], "lane": [int(x) for x in r[2 + 2 * nb:2 + 3 * nb]]}
 
 
+class WarmCompressor:
+    """Reusable gm_compress_warm call (learned warm start and compress in
+    one library call) for a fixed (n_cells, kmax) and model: owns the output
+    record and the workspace."""
+
+    def __init__(self, n_cells, model, device="cuda", **opt):
+        self.opts = make_opts(3, model.kmax, **opt)
+        self.out = MixtureBuffers(n_cells, 3, model.kmax, device)
+        L = _lib.load()
+        nbytes = L.gm_compress_warm_workspace(n_cells, ctypes.byref(self.opts))
+        if nbytes == 0:
+            raise ValueError("invalid options")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.n_cells, self.model = n_cells, model
+        self._mix = self.out.struct()
+
+    def __call__(self, v, alpha, cell_off, stream=None):
+        _need(v, torch.float64, "v")
+        _need(alpha, torch.float64, "alpha")
+        _need(cell_off, torch.int64, "cell_off")
+        if cell_off.numel() != self.n_cells + 1:
+            raise ValueError("cell_off must have n_cells + 1 entries")
+        if v.numel() != alpha.numel() * 3:
+            raise ValueError("v must be [n, 3] with n = len(alpha)")
+        rc = _lib.load().gm_compress_warm(_ptr(v), _ptr(alpha), _ptr(cell_off), self.n_cells, ctypes.byref(self.opts),
+                                          self.model._h, ctypes.byref(self._mix), _ptr(self.ws), self.ws.numel(),
+                                          _stream(stream))
+        check(rc, "gm_compress_warm")
+        return self.out
+
+
 class StandardEM:
     """Reusable standard-EM call (gm_compress_standard) for a fixed batch
     shape: owns the output record, the diagnostics and the workspace."""

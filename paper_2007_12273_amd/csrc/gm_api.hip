@@ -16,6 +16,10 @@ int grid_compress_d1_float(int, int, int, int);
 int grid_compress_d3_float(int, int, int, int);
 int grid_compress_d1_double(int, int, int, int);
 int grid_compress_d3_double(int, int, int, int);
+int launch_compress_big_d1_float(int, const CompressArgs&, int, hipStream_t);
+int launch_compress_big_d3_float(int, const CompressArgs&, int, hipStream_t);
+int launch_compress_big_d1_double(int, const CompressArgs&, int, hipStream_t);
+int launch_compress_big_d3_double(int, const CompressArgs&, int, hipStream_t);
 int launch_compress_pre_d1(const CompressArgs&, hipStream_t);
 int launch_compress_pre_d3(const CompressArgs&, hipStream_t);
 int launch_compress_requeue_d1(const CompressArgs&, hipStream_t);
@@ -56,12 +60,12 @@ struct WsLayout {
 };
 
 // Streams of the EM phase, one set per device: every length bucket runs on
-// a stream of its own (the caller's stream carries the last one), so the
-// twelve bucket launches can run concurrently.  HIP maps streams onto
-// GPU_MAX_HW_QUEUES hardware queues (default 4); the buckets only all run at
-// once with at least twelve.  With fewer, streams share queues round-robin
-// and the launches sharing a queue run one after another.
-constexpr int kLanes = gm::kNumBuckets;
+// a library stream of its own and the big-cell launch on the caller's
+// stream, so the thirteen launches can run concurrently.  HIP maps streams
+// onto GPU_MAX_HW_QUEUES hardware queues (default 4); they only all run at
+// once with at least thirteen.  With fewer, streams share queues
+// round-robin and the launches sharing a queue run one after another.
+constexpr int kLanes = gm::kNumBuckets + 1;
 struct Fork {
     hipStream_t aux[kLanes - 1];
     hipEvent_t fork;
@@ -99,8 +103,10 @@ struct EmPlan {
     bool tuned;
 };
 
-// bucket b on stream b (the largest cells' bucket on the caller's stream)
+// bucket b on library stream b
 constexpr int kNumLaneOf(int b) { return b; }
+// persistent workgroups of the big-cell launch
+constexpr int kBigGrid = 64;
 
 EmPlan default_plan(int kt)
 {
@@ -165,6 +171,16 @@ int launch_em_phase(int D, bool fp64, int kt, const EmPlan& p, gm::CompressArgs&
     for (int i = 0; i < gm::kNumBuckets; ++i) {
         const int b = p.order[i];
         if (launch_em_bucket(D, fp64, kt, b, p, a, n_cells, lanes[p.lane[b]])) return -1;
+    }
+    // cells larger than the buckets hold, on the caller's stream
+    {
+        const int g = (int)std::min<int64_t>(kBigGrid, n_cells);
+        int rc = 0;
+        if (D == 1)
+            rc = fp64 ? gm::launch_compress_big_d1_double(kt, a, g, st) : gm::launch_compress_big_d1_float(kt, a, g, st);
+        else
+            rc = fp64 ? gm::launch_compress_big_d3_double(kt, a, g, st) : gm::launch_compress_big_d3_float(kt, a, g, st);
+        if (rc) return -1;
     }
     for (int i = 0; i < kLanes - 1; ++i) {
         if (hipEventRecord(fk->join[i], fk->aux[i]) != hipSuccess) return -1;
@@ -332,6 +348,61 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
     char* w = scratch_for_device();
     if (!w) return GM_EHIP;
     return compress_run(v, alpha, cell_off, n_cells, o, fixed_sweeps, init, out, w, (hipStream_t)stream);
+}
+
+// ---- warm start + compress in one call ----
+namespace {
+struct WarmWs {
+    size_t feats, frame, Y, K, omega, mu, sigma, fwd, total;
+};
+WarmWs warm_layout(int64_t n_cells, const gm_opts* o)
+{
+    WarmWs w;
+    const size_t n = (size_t)n_cells, km = (size_t)o->kmax;
+    w.feats = ws_layout(n_cells, o->D).total;
+    w.frame = w.feats + align256(n * 128 * sizeof(uint16_t));
+    w.Y = w.frame + align256(n * 9 * sizeof(double));
+    w.K = w.Y + align256(n * 160 * sizeof(float));
+    w.omega = w.K + align256(n * sizeof(int32_t));
+    w.mu = w.omega + align256(n * km * sizeof(double));
+    w.sigma = w.mu + align256(n * km * 3 * sizeof(double));
+    w.fwd = w.sigma + align256(n * km * 6 * sizeof(double));
+    w.total = w.fwd + align256(gm_warm_forward_workspace(n_cells));
+    return w;
+}
+}  // namespace
+
+size_t gm_compress_warm_workspace(int64_t n_cells, const gm_opts* o)
+{
+    if (!valid_opts(o) || o->D != 3 || n_cells < 0) return 0;
+    return warm_layout(n_cells, o).total;
+}
+
+int gm_compress_warm(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
+                     const gm_opts* o, const gm_warm* model, const gm_mix* out, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    int rc = compress_check(v, alpha, cell_off, n_cells, o, nullptr, out);
+    if (rc != GM_OK) return rc;
+    if (!model || o->D != 3 || gm_warm_model_kmax(model) != o->kmax) return GM_EINVAL;
+    if (n_cells == 0) return GM_OK;
+    const WarmWs L = warm_layout(n_cells, o);
+    if (!ws || ws_bytes < L.total) return GM_ENOMEM;
+    char* w = (char*)ws;
+    uint16_t* feats = (uint16_t*)(w + L.feats);
+    double* frame = (double*)(w + L.frame);
+    float* Y = (float*)(w + L.Y);
+    gm_init init;
+    init.K = (const int32_t*)(w + L.K);
+    init.omega = (const double*)(w + L.omega);
+    init.mu = (const double*)(w + L.mu);
+    init.sigma = (const double*)(w + L.sigma);
+    if ((rc = gm_warm_features(v, alpha, cell_off, n_cells, 3, feats, frame, stream)) != GM_OK) return rc;
+    if ((rc = gm_warm_forward(model, feats, n_cells, Y, w + L.fwd, L.total - L.fwd, stream)) != GM_OK) return rc;
+    if ((rc = gm_warm_decode(Y, frame, cell_off, n_cells, o->kmax, (int32_t*)(w + L.K), (double*)(w + L.omega),
+                             (double*)(w + L.mu), (double*)(w + L.sigma), stream)) != GM_OK)
+        return rc;
+    return compress_run(v, alpha, cell_off, n_cells, o, nullptr, &init, out, w, (hipStream_t)stream);
 }
 
 size_t gm_compress_standard_workspace(int64_t n_cells, int64_t n_tot, const gm_opts* o)

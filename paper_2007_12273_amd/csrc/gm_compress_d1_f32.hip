@@ -23,4 +23,10 @@ int launch_compress_finish_d1(int kmax_tpl, const CompressArgs& a, hipStream_t s
     return launch_finish_dr<1>(kmax_tpl, a, st);
 }
 
+
+int launch_compress_big_d1_float(int kmax_tpl, const CompressArgs& a, int grid, hipStream_t st)
+{
+    return launch_big_dr<1, float>(kmax_tpl, a, grid, st);
+}
+
 }  // namespace gm

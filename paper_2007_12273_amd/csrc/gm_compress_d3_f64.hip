@@ -14,4 +14,10 @@ int grid_compress_d3_double(int kmax_tpl, int per_thread, int mode, int waves)
     return grid_dr<3, double>(kmax_tpl, per_thread, mode, waves);
 }
 
+
+int launch_compress_big_d3_double(int kmax_tpl, const CompressArgs& a, int grid, hipStream_t st)
+{
+    return launch_big_dr<3, double>(kmax_tpl, a, grid, st);
+}
+
 }  // namespace gm

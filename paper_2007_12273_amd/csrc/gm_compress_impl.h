@@ -61,7 +61,10 @@ struct CellInfo {
     int32_t n;
 };
 
-enum { CELL_EM = 0, CELL_CLOSED = 1, CELL_INVALID = 2, CELL_EMPTY = 3, CELL_OVERSIZE = 4 };
+// CELL_BIG: more particles than the register-resident EM launches hold
+// (kMaxCellParticles), fitted by k_em_big; CELL_OVERSIZE: a cell the
+// standard EM's staging buffers do not reach (no mixture)
+enum { CELL_EM = 0, CELL_CLOSED = 1, CELL_INVALID = 2, CELL_EMPTY = 3, CELL_OVERSIZE = 4, CELL_BIG = 5 };
 
 struct CompressArgs {
     const double* v;
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs
     const int64_t n64 = A.off[c + 1] - o0;
     CellInfo<D>* ci = static_cast<CellInfo<D>*>(A.cells) + c;
     double* mom = A.out.moments + (size_t)c * NM;
-    if (n64 <= 0 || n64 > kMaxCellParticles) {
+    if (n64 <= 0 || n64 > 0x7fffffff) {
         if (lane < NM) mom[lane] = 0.0;
         if (lane == 0) {
             ci->kind = n64 == 0 ? CELL_EMPTY : CELL_OVERSIZE;
@@ -208,8 +211,9 @@ __global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs
         ci->trC = tr;
         ci->W = W;
         ci->n = n;
-        ci->kind = closed ? CELL_CLOSED : CELL_EM;
-        if (!closed) atomicAdd(&A.plan[PLAN_COUNT + bucket_of(A.kmax <= 8 ? 8 : 16, n)], 1);
+        const bool big = n > kMaxCellParticles;
+        ci->kind = closed ? CELL_CLOSED : (big ? CELL_BIG : CELL_EM);
+        if (!closed) atomicAdd(&A.plan[PLAN_COUNT + (big ? kNumBuckets : bucket_of(A.kmax <= 8 ? 8 : 16, n))], 1);
     }
     if (closed) return;
     // cold start: min(kmax, n, floor(N/T)) distinct particles by a partial
@@ -257,11 +261,12 @@ __global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs
     }
 }
 
-// bucket bases and queue resets (one thread)
+// bucket bases and queue resets (one thread); slot kNumBuckets lists the
+// cells larger than the buckets hold
 static __global__ void k_plan_scan(int32_t* plan)
 {
     int base = 0;
-    for (int b = 0; b < kNumBuckets; ++b) {
+    for (int b = 0; b <= kNumBuckets; ++b) {
         plan[PLAN_BASE + b] = base;
         plan[PLAN_CURSOR + b] = 0;
         plan[PLAN_QUEUE + b] = 0;
@@ -281,6 +286,7 @@ __global__ void k_plan_scatter(CompressArgs A)
     if (c < A.n_cells) {
         const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
         if (ci->kind == CELL_EM) b = bucket_of(A.kmax <= 8 ? 8 : 16, ci->n);
+        else if (ci->kind == CELL_BIG) b = kNumBuckets;
     }
     uint64_t todo = __builtin_amdgcn_ballot_w64(b >= 0);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -304,7 +310,7 @@ static __global__ void k_plan_reset(int32_t* plan)
 // rewind every bucket's work queue (the autotuner reruns the EM launches)
 static __global__ void k_plan_requeue(int32_t* plan)
 {
-    if (threadIdx.x < kNumBuckets) plan[PLAN_QUEUE + threadIdx.x] = 0;
+    if (threadIdx.x <= kNumBuckets) plan[PLAN_QUEUE + threadIdx.x] = 0;
 }
 
 template <int D>
@@ -670,6 +676,22 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_wave
         const int fixed = A.fixed ? A.fixed[c] : 0;
         const double L_one = N * (lnc0 - 0.5 * D) - halfT * log(N);
         bool warm = A.init.K != nullptr && A.init.K[c] > 0;
+        // A supplied start is used only if eq. (omegak) is defined for it:
+        // N - T K / 2 > 0 and N w_k > T/2 for every supplied component
+        // (weights renormalised over the K used); otherwise the cell starts
+        // cold, flagged as a rejected warm start.
+        if (warm) {
+            const int Kw = min(A.init.K[c], kmax);
+            const size_t s0 = (size_t)c * kmax;
+            double wsum = 0.0;
+            for (int j = 0; j < Kw; ++j) wsum += A.init.omega[s0 + j];
+            bool usable = N - halfT * Kw > 0.0 && wsum > 0.0 && isfinite(wsum);
+            for (int j = 0; j < Kw; ++j) usable &= N * (A.init.omega[s0 + j] / wsum) > halfT;
+            if (!usable) {
+                warm = false;
+                status = GM_ST_WARM_FALLBACK;
+            }
+        }
         long long visits = 0;
         double L_s = 0.0;
         int s = 0;
@@ -1139,6 +1161,329 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_wave
 }
 
 // ===========================================================================
+// k_em_big: the sweeps of cells larger than the register-resident launches
+// hold (n > kMaxCellParticles).  Persistent 1024-thread workgroups take cells
+// from the big-cell queue.  No per-particle state is kept: every pass reads
+// the cell's particles from the input, and every E-step forms each
+// particle's mixture denominator from all live components by a base-2
+// log-sum-exp, so the cost per component update grows with K, which these
+// rare cells can afford.  Start, M-step, annihilation, weights, objective,
+// stop test, warm-start acceptance and the outer search over K are those of
+// k_em; the penalised state goes into the record for k_finish.
+// ===========================================================================
+constexpr int kBigBucket = kNumBuckets;  // plan slot of the big cells
+constexpr int kBigThreads = 1024;
+
+template <int D, int KMAX, typename R>
+__global__ __launch_bounds__(kBigThreads) void k_em_big(CompressArgs A)
+{
+    constexpr int NT = ntri(D);
+    constexpr int NS = 1 + D + NT;
+    constexpr int NW = kBigThreads / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const double T = 0.5 * D * (D + 3);
+    const double halfT = 0.5 * T;
+    __shared__ CompState<R, D> comp[KMAX];
+    __shared__ CompState<R, D> bestc[KMAX];
+    __shared__ R red_r[2 * kMaxWaves * 16];
+    __shared__ double red_d[2 * kMaxWaves * 2];
+    __shared__ int s_idx, s_flag;
+    int par_r = 0, par_d = 0;
+    const int count = A.plan[PLAN_COUNT + kBigBucket];
+    const int base = A.plan[PLAN_BASE + kBigBucket];
+
+    for (;;) {
+        if (tid == 0) s_idx = atomicAdd(&A.plan[PLAN_QUEUE + kBigBucket], 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;
+        const int c = A.list[base + idx];
+        const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
+        const int n = ci->n;
+        const double trC = ci->trC;
+        const double sdc64 = sqrt_det<D>(ci->C);
+        const R sdc = (R)sdc64;
+        const double lnc0 = -0.5 * D * kLnTwoPi - log(sdc64);
+        const double lnN = log((double)n);
+        const double N = (double)n;
+        const double wscale = N / ci->W;
+        const int64_t o0 = A.off[c];
+        const double* vc = A.v + o0 * D;
+        const double* ac = A.alpha + o0;
+        const int kmax = A.kmax;
+        double m[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) m[d] = ci->m[d];
+        // particle i: centred velocity and normalised weight in R
+        auto load = [&](int i, R (&x)[D], R& a) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) x[d] = (R)(vc[(size_t)i * D + d] - m[d]);
+            a = (R)(ac[i] * wscale);
+        };
+        int32_t status = 0;
+        const int fixed = A.fixed ? A.fixed[c] : 0;
+        const double L_one = N * (lnc0 - 0.5 * D) - halfT * log(N);
+        bool warm = A.init.K != nullptr && A.init.K[c] > 0;
+        // A supplied start is used only if eq. (omegak) is defined for it:
+        // N - T K / 2 > 0 and N w_k > T/2 for every supplied component
+        // (weights renormalised over the K used); otherwise the cell starts
+        // cold, flagged as a rejected warm start.
+        if (warm) {
+            const int Kw = min(A.init.K[c], kmax);
+            const size_t s0 = (size_t)c * kmax;
+            double wsum = 0.0;
+            for (int j = 0; j < Kw; ++j) wsum += A.init.omega[s0 + j];
+            bool usable = N - halfT * Kw > 0.0 && wsum > 0.0 && isfinite(wsum);
+            for (int j = 0; j < Kw; ++j) usable &= N * (A.init.omega[s0 + j] / wsum) > halfT;
+            if (!usable) {
+                warm = false;
+                status = GM_ST_WARM_FALLBACK;
+            }
+        }
+        long long visits = 0;
+        double L_s = 0.0;
+        int s = 0, K = 0;
+        R G = R(0);
+        for (;;) {
+            // ---------------- initial mixture (as in k_em) ------------------
+            if (tid == 0) s_flag = 0;
+            if (warm) {
+                K = min(A.init.K[c], kmax);
+            } else {
+                K = min(kmax, n);
+                const int cap = max(1, (int)floor(N / T));
+                if (K > cap) {
+                    K = cap;
+                    status |= GM_ST_K0_CAPPED;
+                }
+            }
+            __syncthreads();
+            if (tid < K) {
+                CompState<R, D> cs;
+                if (warm) {
+                    const size_t s0 = (size_t)c * kmax;
+                    double wsum = 0.0;
+                    for (int j = 0; j < K; ++j) wsum += A.init.omega[s0 + j];
+                    const size_t sk = s0 + tid;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) cs.mu[d] = (R)(A.init.mu[sk * D + d] - m[d]);
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) cs.S[q] = (R)A.init.sigma[sk * NT + q];
+                    cs.u = (R)(A.init.omega[sk] / wsum);
+                } else {
+                    const int ip = A.init_idx[(size_t)c * kInitSlots + tid];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) cs.mu[d] = (R)(vc[(size_t)ip * D + d] - m[d]);
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) cs.S[q] = (R)ci->C[q];
+                    cs.u = (R)(1.0 / K);
+                }
+                if (factor_comp<R, D>(cs, trC, sdc)) s_flag = 1;
+                comp[tid] = cs;
+            }
+            __syncthreads();
+            if (s_flag) status |= GM_ST_COV_FLOOR;
+            G = R(0);
+            for (int j = 0; j < K; ++j) G += comp[j].u;
+
+            const bool outer = A.outer != 0 && fixed <= 0;
+            double L_best = -INFINITY;
+            int K_best = 0, s_total = 0;
+            R G_best = R(0);
+            for (;;) {
+                R inv_den = m_rcp((R)(N - halfT * K));
+                const int cap_sweeps = fixed > 0 ? fixed : A.max_sweeps;
+                int Kslots = K;
+                uint32_t alive = (1u << K) - 1u;
+                // base-2 log-sum-exp over the live slots at x: returns the
+                // largest term in mx and sum_j 2^(t_j - mx)
+                auto lse2 = [&](const R (&x)[D], R& mx) {
+                    mx = R(-INFINITY);
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) mx = fmax(mx, log2_term<R, D>(comp[j], x));
+                    R se = R(0);
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) se += fast_exp2(log2_term<R, D>(comp[j], x) - mx);
+                    return se;
+                };
+                double L_prev = 0.0;
+                for (s = 1; s <= cap_sweeps; ++s) {
+                    bool annihilated = false;
+                    for (int k = 0; k < Kslots; ++k) {
+                        if (!((alive >> k) & 1u)) continue;
+                        ++visits;
+                        const CompState<R, D> ck = comp[k];
+                        R sums[NS];
+#pragma unroll
+                        for (int t = 0; t < NS; ++t) sums[t] = R(0);
+                        for (int i = tid; i < n; i += kBigThreads) {
+                            R x[D], a;
+                            load(i, x, a);
+                            R mx;
+                            const R se = lse2(x, mx);
+                            const R g = a * fast_exp2(log2_term<R, D>(ck, x) - mx) / se;
+                            R d[D];
+#pragma unroll
+                            for (int q = 0; q < D; ++q) d[q] = x[q] - ck.mu[q];
+                            sums[0] += g;
+#pragma unroll
+                            for (int q = 0; q < D; ++q) {
+                                const R gd = g * d[q];
+                                sums[1 + q] += gd;
+#pragma unroll
+                                for (int r = q; r < D; ++r) sums[1 + D + tri_idx<D>(q, r)] += gd * d[r];
+                            }
+                        }
+                        block_sum<16>(sums, red_r, par_r, NW);
+                        const R Nk = sums[0];
+                        const R NkT = Nk - (R)halfT;
+                        if (fabs(NkT) < (R)(1e-5 * halfT)) status |= GM_ST_NEAR_TIE;
+                        if (NkT <= R(0)) {
+                            // annihilate k (eq. omegak); the weights renormalise through G
+                            alive &= ~(1u << k);
+                            G -= ck.u;
+                            --K;
+                            inv_den = m_rcp((R)(N - halfT * K));
+                            annihilated = true;
+                            continue;
+                        }
+                        // M-step (eqs. muk, sigmak about the new mean; eq. omegak)
+                        CompState<R, D> cn;
+                        const R invN = m_rcp(Nk);
+                        R dl[D];
+#pragma unroll
+                        for (int q = 0; q < D; ++q) {
+                            dl[q] = sums[1 + q] * invN;
+                            cn.mu[q] = ck.mu[q] + dl[q];
+                        }
+#pragma unroll
+                        for (int q = 0; q < D; ++q)
+#pragma unroll
+                            for (int r = q; r < D; ++r)
+                                cn.S[tri_idx<D>(q, r)] = sums[1 + D + tri_idx<D>(q, r)] * invN - dl[q] * dl[r];
+                        const R unew = NkT * inv_den * G;
+                        G = G - ck.u + unew;
+                        cn.u = unew;
+                        if (factor_comp<R, D>(cn, trC, sdc)) status |= GM_ST_COV_FLOOR;
+                        __syncthreads();  // every thread has read comp[k] for this update
+                        if (tid == 0) comp[k] = cn;
+                        __syncthreads();
+                    }
+                    // ---- end of sweep: eq. (lnL-GM) with the normalised weights ----
+                    const R lg2G = fast_log2(G);
+                    double lsum[1] = {0.0};
+                    for (int i = tid; i < n; i += kBigThreads) {
+                        R x[D], a;
+                        load(i, x, a);
+                        R mx;
+                        const R se = lse2(x, mx);
+                        lsum[0] += (double)a * (double)(mx + fast_log2(se) - lg2G);
+                    }
+                    block_sum<2>(lsum, red_d, par_d, NW);
+                    __syncthreads();
+                    if (tid < Kslots && ((alive >> tid) & 1u)) {
+                        comp[tid].u = comp[tid].u * m_rcp(G);
+                        comp[tid].c2 = comp[tid].c2 - lg2G;
+                    }
+                    __syncthreads();
+                    R Gn = R(0);
+                    double pen = 0.0;
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) Gn += comp[j].u;
+                    for (int j = 0; j < Kslots; ++j)
+                        if ((alive >> j) & 1u) pen += (double)fast_log2(comp[j].u * m_rcp(Gn));
+                    G = Gn;
+                    const double dpar = K * T + K - 1;
+                    L_s = kLn2 * (lsum[0] - 0.5 * T * pen) + N * lnc0 - 0.5 * dpar * lnN;
+                    // ---- compaction of dead slots, order kept ----
+                    if (annihilated) {
+                        __syncthreads();
+                        if (tid == 0) {
+                            int w = 0;
+                            for (int j = 0; j < Kslots; ++j)
+                                if ((alive >> j) & 1u) comp[w++] = comp[j];
+                        }
+                        __syncthreads();
+                        Kslots = K;
+                        alive = (1u << K) - 1u;
+                    }
+                    if (fixed > 0) {
+                        if (s == fixed) break;
+                        L_prev = L_s;
+                        continue;
+                    }
+                    if (!isfinite(L_s)) break;
+                    if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= A.tol * fabs(L_s)) break;
+                    if (s == A.max_sweeps) {
+                        status |= GM_ST_MAXSWEEPS;
+                        break;
+                    }
+                    L_prev = L_s;
+                }
+                if (s > cap_sweeps) s = cap_sweeps;
+                s_total += s;
+                if (!outer) break;
+                if (K_best == 0 || L_s > L_best) {
+                    __syncthreads();
+                    if (tid < K) bestc[tid] = comp[tid];
+                    L_best = L_s;
+                    K_best = K;
+                    G_best = G;
+                }
+                if (K <= 1 || !isfinite(L_s)) break;
+                // remove the least probable component (smallest weight, lowest slot on ties)
+                int kmin = 0;
+                R umin = comp[0].u;
+                for (int j = 1; j < K; ++j) {
+                    const R uj = comp[j].u;
+                    if (uj < umin) {
+                        umin = uj;
+                        kmin = j;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0)
+                    for (int j = kmin; j + 1 < K; ++j) comp[j] = comp[j + 1];
+                __syncthreads();
+                G -= umin;
+                --K;
+            }
+            if (outer && K_best > 0) {
+                __syncthreads();
+                if (tid < K_best) comp[tid] = bestc[tid];
+                __syncthreads();
+                K = K_best;
+                G = G_best;
+                L_s = L_best;
+            }
+            s = s_total;
+            if (!warm || fixed > 0 || L_s >= L_one - 1e-5 * fabs(L_one)) break;
+            warm = false;
+            status = GM_ST_WARM_FALLBACK;
+            __syncthreads();
+        }
+        // penalised state into the output record (centred coordinates)
+        if (tid < K) {
+            const size_t sk = (size_t)c * kmax + tid;
+            const CompState<R, D> cs = comp[tid];
+            A.out.omega[sk] = (double)cs.u / (double)G;
+            for (int d = 0; d < D; ++d) A.out.mu[sk * D + d] = (double)cs.mu[d];
+            for (int q = 0; q < NT; ++q) A.out.sigma[sk * NT + q] = (double)cs.S[q];
+        }
+        if (tid == 0) {
+            A.out.K[c] = K;
+            A.out.L_pen[c] = L_s;
+            A.out.sweeps[c] = s;
+            A.out.visits[c] = visits;
+            A.out.status[c] = status;
+        }
+        __syncthreads();
+    }
+}
+
+// ===========================================================================
 // k_finish
 // ===========================================================================
 template <int D>
@@ -1527,6 +1872,18 @@ int grid_dr(int kmax_tpl, int per_thread, int mode, int waves)
     if (nb < 1) nb = 1;
     slot = nb * ncu;
     return slot;
+}
+
+// the big-cell sweeps: `grid` persistent workgroups (they leave at once when
+// the batch has no big cell)
+template <int D, typename R>
+int launch_big_dr(int kmax_tpl, const CompressArgs& a, int grid, hipStream_t st)
+{
+    if (kmax_tpl == 8)
+        hipLaunchKernelGGL((k_em_big<D, 8, R>), dim3(grid), dim3(kBigThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_em_big<D, 16, R>), dim3(grid), dim3(kBigThreads), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // pre- and post-EM kernels of one D

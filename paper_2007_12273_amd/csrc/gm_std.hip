@@ -43,7 +43,7 @@ __global__ void k_std_stage(StdArgs P)
     const CompressArgs& A = P.a;
     const int c = blockIdx.x;
     CellInfo<D>* ci = static_cast<CellInfo<D>*>(A.cells) + c;
-    if (ci->kind != CELL_EM) return;
+    if (ci->kind != CELL_EM && ci->kind != CELL_BIG) return;
     if (A.off[c + 1] > P.n_tot) {
         __syncthreads();
         if (threadIdx.x == 0) ci->kind = CELL_OVERSIZE;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kStdThreads) void k_std(StdArgs P)
     const int lane = tid & 63, wid = tid >> 6;
     const int c = blockIdx.x;
     const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
-    if (ci->kind != CELL_EM) return;
+    if (ci->kind != CELL_EM && ci->kind != CELL_BIG) return;
 
     __shared__ CompState<float, D> comp[KMAX];
     __shared__ double th[LEN];                  // theta_i, component k at k * L

@@ -741,6 +741,8 @@ int gm_warm_forward(const gm_warm* m, const uint16_t* feats, int64_t n_rows, flo
     return forward(m, feats, (int)n_rows, H1b, nullptr, H2b, nullptr, Y, (hipStream_t)stream);
 }
 
+int gm_warm_model_kmax(const gm_warm* m) { return m ? m->kmax : 0; }
+
 size_t gm_warm_forward_workspace(int64_t n_rows)
 {
     if (n_rows < 0) return 0;

@@ -4,9 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# hardware queues for the twelve concurrent length-bucket launches of the EM
+# hardware queues for the thirteen concurrent launches of the EM
 # phase, read when the HIP runtime starts (before any test touches the GPU)
-if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 12:
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 13:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -58,7 +58,10 @@ def _errs(a, b, c, D):
 
 
 def _lerr(a, b, c, n):
-    return max(abs(a["L_pen"][c] - b["L_pen"][c]), abs(a["L_final"][c] - b["L_final"][c])) / max(abs(b["L_pen"][c]), n)
+    vals = (a["L_pen"][c], b["L_pen"][c], a["L_final"][c], b["L_final"][c])
+    if not all(np.isfinite(vals)):
+        return 0.0 if vals[0] == vals[1] and vals[2] == vals[3] else np.inf
+    return max(abs(vals[0] - vals[1]), abs(vals[2] - vals[3])) / max(abs(vals[1]), n)
 
 
 def resolution(d, kmax, seed, sweeps, ref, **kw):

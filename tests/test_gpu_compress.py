@@ -185,10 +185,20 @@ def test_edge_cells_and_all_buckets():
         assert np.array_equal(g["sweeps"], o["sweeps"])
         res = fp32_parity.resolution(d, kmax, 11, o["sweeps"], o)
         fp32_parity.check(g, o, d, res, "edge kmax=%d" % kmax)
-    # oversize cell
-    big = synth.random_cells(7, 1, D, 9000, 9000)
-    g = _gpu_compress(big, 8, seed=1)
-    assert g["K"][0] == 0 and g["status"][0] == oracle.STATUS["DEGENERATE"]
+
+
+def test_cells_larger_than_the_buckets():
+    """Cells of more than 8192 particles (the register-resident launches'
+    limit) run in the streaming launch: FP32 replay of the oracle's sweeps
+    with the FP32 bars, in a batch that also holds bucket-sized cells."""
+    parts = [synth.random_cells(700 + i, 1, 3, n, n, k_lo=1, k_hi=3) for i, n in enumerate((8193, 11000, 500))]
+    d = synth.concat_cells(parts)
+    for kmax in (8, 16):
+        o = oracle.compress(d["v"], d["alpha"], d["cell_off"], kmax=kmax, seed=13, max_sweeps=60)
+        g = _gpu_compress(d, kmax, seed=13, fixed_sweeps=o["sweeps"], max_sweeps=60)
+        assert np.array_equal(g["sweeps"], o["sweeps"]) and np.array_equal(g["visits"], o["visits"])
+        res = fp32_parity.resolution(d, kmax, 13, o["sweeps"], o)
+        fp32_parity.check(g, o, d, res, "big cells kmax=%d" % kmax)
 
 
 def test_warm_init_matches_oracle():

@@ -17,7 +17,8 @@ Batches cover every length bucket of both component-slot classes:
 Weibel-like 1D3V cells (kmax 16) and 2D3V grid cells (kmax 8) picked by
 size from the workload generators, plus cells of the same recipes drawn at
 sizes the workloads rarely or never reach (11-200 and 4100-8192
-particles), in converged mode and in replay of the oracle's sweep counts;
+particles, and above 8192, where the streaming launch takes over), in
+converged mode and in replay of the oracle's sweep counts;
 also the 1D1V mixed workload, supplied starting mixtures and the outer
 search over K.
 """
@@ -132,6 +133,14 @@ def test_grid_3v_every_bucket_fp64_exact():
                          k_lo=1, k_hi=4, aniso=False)
     d = _covering_batch(synth.grid_3v(n_cells=8192), BUCKETS8, small, big)
     _both_modes(d, 8, 2004, "grid kmax 8")
+
+
+def test_cells_larger_than_the_buckets_fp64_exact():
+    """Cells of 8193 to 16384 particles (the streaming launch) among
+    bucket-sized ones, 3V and 1V."""
+    for D, kmax, seed in ((3, 16, 310), (3, 8, 320), (1, 8, 330)):
+        d = _one_per_range(seed, D, [(8193, 9000), (9001, 16384), (300, 2000)], k_lo=1, k_hi=3, aniso=False)
+        _both_modes(d, kmax, seed, "cells above 8192, D %d kmax %d" % (D, kmax))
 
 
 def test_mix_1v_fp64_exact():

@@ -369,3 +369,59 @@ def test_training_lowers_the_loss():
     print("training loss %.4f -> %.4f" % (first, last))
     assert np.isfinite(last) and last < 0.7 * first
     m.close()
+
+
+def test_single_call_warm_compress_equals_composed_path():
+    """gm_compress_warm (features, network, decode and compress in one
+    library call) gives the record of the composed calls bit for bit, and
+    rejects a kmax other than the model's."""
+    api = _api()
+    d = _subset(synth.make("weibel_3v"), 200)
+    v, a, off = to_gpu(d)
+    tr = _subset(synth.make("weibel_3v", seed=5002), 1024)
+    from paper_2007_12273_amd import warm as warmlib
+    feats, targs = warmlib.training_set([tr], 16, seed=2003, device=dev())
+    m = api.WarmStart(16, batch=256, seed=7, device=dev())
+    warmlib.train(m, feats, targs, epochs=3)
+    ref = host(api.compress(v, a, off, 16, seed=2003, init=m.initial_mixtures(v, a, off)))
+    wc = api.WarmCompressor(200, m, device=dev(), seed=2003)
+    got = host(wc(v, a, off).as_dict())
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    assert (got["K"] > 0).all()
+    import ctypes
+    from paper_2007_12273_amd import _lib
+    bad = api.make_opts(3, 8)
+    mix = wc.out.struct()
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert _lib.load().gm_compress_warm(P(v), P(a), P(off), 200, ctypes.byref(bad), m._h, ctypes.byref(mix), P(wc.ws),
+                                        wc.ws.numel(), None) == _lib.GM_EINVAL
+    m.close()
+
+
+def test_unusable_supplied_start_starts_cold_on_gpu():
+    """Supplied starts for which eq. (omegak) is undefined (N - T K / 2 <= 0,
+    or a component with N w_k <= T/2) are not used: those cells give the cold
+    fit bit for bit, flagged as rejected warm starts, as in the oracle."""
+    d = synth.concat_cells([synth.random_cells(21 + i, 1, 3, m, m, k_lo=1, k_hi=2) for i, m in enumerate((50, 300, 300))])
+    off = d["cell_off"]
+    kmax = 16
+    init = {"K": np.array([16, 2, 1], np.int32), "omega": np.zeros((3, kmax)), "mu": np.zeros((3, kmax, 3)),
+            "sigma": np.zeros((3, kmax, 6))}
+    for c in range(3):
+        init["mu"][c, :] = d["v"][off[c]:off[c + 1]].mean(0)
+        init["sigma"][c, :] = [0.01, 0, 0, 0.01, 0, 0.01]
+    init["omega"][0, :16] = 1.0 / 16
+    init["omega"][1, :2] = [1.0, 4.0 / 300]
+    init["omega"][2, 0] = 1.0
+    v, a, offg = to_gpu(d)
+    api = _api()
+    cold = host(api.compress(v, a, offg, kmax, seed=4, max_sweeps=50))
+    g = host(api.compress(v, a, offg, kmax, seed=4, max_sweeps=50, init=_to_dev(init)))
+    o = oracle.compress(d["v"], d["alpha"], off, kmax=kmax, seed=4, max_sweeps=50, init=init)
+    np.testing.assert_array_equal(g["status"] & FALLBACK, o["status"] & FALLBACK)
+    assert (g["status"][:2] & FALLBACK).all() and not (g["status"][2] & FALLBACK)
+    for c in (0, 1):
+        for k in ("K", "sweeps", "visits", "omega", "mu", "sigma", "L_pen", "L_final"):
+            assert np.array_equal(g[k][c], cold[k][c]), (c, k)
+        assert g["status"][c] == cold["status"][c] | FALLBACK

@@ -551,3 +551,37 @@ def test_likelihood_shifts_with_the_velocity_unit(name):
     np.testing.assert_allclose(r2["omega"], r1["omega"], rtol=0, atol=1e-10)
     np.testing.assert_allclose(r2["mu"], s * r1["mu"], rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(r2["sigma"], s * s * r1["sigma"], rtol=1e-9, atol=1e-14)
+
+
+def test_unusable_supplied_start_starts_cold():
+    """A supplied start for which eq. (omegak) is undefined -- N - T K / 2 <= 0
+    (sixteen components on a 50-particle 3V cell, T = 9) or a component with
+    N w_k <= T/2 -- is not used: the cell is fitted from the cold start, as
+    a cell without a supplied start is, and flagged as a rejected warm start."""
+    d = synth.concat_cells([synth.random_cells(21 + i, 1, 3, m, m, k_lo=1, k_hi=2) for i, m in enumerate((50, 300, 300))])
+    off = d["cell_off"]
+    n = np.diff(off)
+    kmax = 16
+    cold = oracle.compress(d["v"], d["alpha"], off, kmax=kmax, seed=4, max_sweeps=50)
+    init = {"K": np.zeros(3, np.int32), "omega": np.zeros((3, kmax)), "mu": np.zeros((3, kmax, 3)),
+            "sigma": np.zeros((3, kmax, 6))}
+    for c in range(3):
+        m = d["v"][off[c]:off[c + 1]].mean(0)
+        init["mu"][c, :] = m
+        init["sigma"][c, :] = [0.01, 0, 0, 0.01, 0, 0.01]
+    init["K"][0] = 16                      # N - T K / 2 = 50 - 72 < 0
+    init["omega"][0, :16] = 1.0 / 16
+    init["K"][1] = 2                       # second component: N w = 300 * 0.0132 = 3.95 <= T/2
+    init["omega"][1, :2] = [1.0, 4.0 / 300]
+    init["K"][2] = 1                       # a usable single-component start
+    init["omega"][2, 0] = 1.0
+    r = oracle.compress(d["v"], d["alpha"], off, kmax=kmax, seed=4, max_sweeps=50, init=init)
+    fb = oracle.STATUS["WARM_FALLBACK"]
+    for c in (0, 1):
+        bad = n[c] - 4.5 * min(init["K"][c], kmax) <= 0 or any(
+            n[c] * init["omega"][c, k] / init["omega"][c, :init["K"][c]].sum() <= 4.5 for k in range(init["K"][c]))
+        assert bad
+        assert r["status"][c] & fb
+        for k in ("K", "sweeps", "visits", "omega", "mu", "sigma", "L_pen"):
+            assert np.array_equal(r[k][c], cold[k][c]), (c, k)
+    assert not (r["status"][2] & fb)
