@@ -396,21 +396,28 @@ int gm_warm_model_kmax(const gm_warm* model);
  * gm_compress_warm -- the learned warm start and the compress in one call
  * (the warm path of the compress entry point: gm_compress with a model
  * handle).  Enqueues on `stream`: features of every cell (gm_warm_features),
- * the network (gm_warm_forward), decode into initial mixtures
- * (gm_warm_decode), then gm_compress from those mixtures (converged mode;
+ * the network and the decode into initial mixtures (gm_warm_infer), then
+ * gm_compress from those mixtures (converged mode;
  * a cell whose warm fit ends below the single Gaussian is refitted from the
  * cold start and flagged GM_ST_WARM_FALLBACK, see gm_init).  The result is
  * the one gm_compress gives for the decoded mixtures.  Arguments as for
  * gm_compress; o->D must be 3 and o->kmax the model's kmax (GM_EINVAL
  * otherwise).  ws: device workspace of at least
  * gm_compress_warm_workspace(n_cells, o) bytes holding the compress
- * workspace, the features, frames, network outputs and decoded mixtures.
+ * workspace, the features, frames and decoded mixtures.
  * The model is only read (its weights); calls on one model may overlap.
  */
 size_t gm_compress_warm_workspace(int64_t n_cells, const gm_opts* o);
 int gm_compress_warm(const double* v, const double* alpha, const int64_t* cell_off, int64_t n_cells,
                      const gm_opts* o, const gm_warm* model, const gm_mix* out, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* Network and decode fused (one launch, 32 cells per workgroup, the
+ * activations in LDS): the initial mixtures gm_warm_forward followed by
+ * gm_warm_decode give, bit for bit, without the FP32 network outputs
+ * leaving the chip.  Arguments as for those two calls. */
+int gm_warm_infer(const gm_warm* model, const uint16_t* feats, const double* frame, const int64_t* cell_off,
+                  int64_t n_cells, int32_t kmax, int32_t* K, double* omega, double* mu, double* sigma, void* stream);
 
 /* Training targets [n_cells * 160] FP32 from fitted mixtures (gm_mix
  * layout, kmax slots) and frames.  A component whose whitened covariance

@@ -42,7 +42,7 @@ class GmInit(ctypes.Structure):
 
 
 EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_compress_noalloc", "gm_compress_warm",
-           "gm_compress_warm_workspace", "gm_warm_model_kmax", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
+           "gm_compress_warm_workspace", "gm_warm_model_kmax", "gm_warm_infer", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
@@ -81,6 +81,8 @@ def load():
     L.gm_compress_warm.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), P, ctypes.POINTER(GmMix), P,
                                    ctypes.c_size_t, P]
     L.gm_compress_warm.restype = ctypes.c_int
+    L.gm_warm_infer.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]
+    L.gm_warm_infer.restype = ctypes.c_int
     L.gm_warm_model_kmax.argtypes = [P]
     L.gm_warm_model_kmax.restype = ctypes.c_int
     L.gm_autotune.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(GmOpts), ctypes.POINTER(GmInit),

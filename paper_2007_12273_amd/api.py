@@ -552,15 +552,28 @@ class WarmStart:
                               loss.ctypes.data, _stream(stream)), "gm_warm_train")
         return [float(x) for x in loss]
 
+    def infer(self, feats, frame, cell_off, out, stream=None):
+        """Network and decode fused (gm_warm_infer) into `out` (a gm_init
+        dict of device tensors, kmax slots)."""
+        _need(feats, torch.int16, "feats")
+        n = feats.shape[0]
+        if feats.shape[1] != NFEAT_ROW or frame.shape != (n, 9) or cell_off.numel() != n + 1:
+            raise ValueError("features [n, 128], frame [n, 9] and cell_off [n + 1] expected")
+        rc = _lib.load().gm_warm_infer(self._h, _ptr(feats), _ptr(frame), _ptr(cell_off), n, self.kmax,
+                                       _ptr(out["K"]), _ptr(out["omega"]), _ptr(out["mu"]), _ptr(out["sigma"]),
+                                       _stream(stream))
+        check(rc, "gm_warm_infer")
+        return out
+
     def initial_mixtures(self, v, alpha, cell_off, bufs=None, stream=None):
-        """features -> forward -> decode: a gm_init record for compress.
-        `bufs` (from init_buffers) makes repeated calls allocation-free."""
+        """features -> network and decode (fused): a gm_init record for
+        compress.  `bufs` (from init_buffers) makes repeated calls
+        allocation-free."""
         n_cells = cell_off.numel() - 1
         if bufs is None:
             bufs = self.init_buffers(n_cells)
         warm_features(v, alpha, cell_off, feats=bufs["feats"], frame=bufs["frame"], stream=stream)
-        self.forward(bufs["feats"], Y=bufs["Y"], stream=stream)
-        return warm_decode(bufs["Y"], bufs["frame"], cell_off, self.kmax, out=bufs["init"], stream=stream)
+        return self.infer(bufs["feats"], bufs["frame"], cell_off, bufs["init"], stream=stream)
 
     def init_buffers(self, n_cells):
         dev = self.device

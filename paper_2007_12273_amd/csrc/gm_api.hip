@@ -353,7 +353,7 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
 // ---- warm start + compress in one call ----
 namespace {
 struct WarmWs {
-    size_t feats, frame, Y, K, omega, mu, sigma, fwd, total;
+    size_t feats, frame, K, omega, mu, sigma, total;
 };
 WarmWs warm_layout(int64_t n_cells, const gm_opts* o)
 {
@@ -361,13 +361,11 @@ WarmWs warm_layout(int64_t n_cells, const gm_opts* o)
     const size_t n = (size_t)n_cells, km = (size_t)o->kmax;
     w.feats = ws_layout(n_cells, o->D).total;
     w.frame = w.feats + align256(n * 128 * sizeof(uint16_t));
-    w.Y = w.frame + align256(n * 9 * sizeof(double));
-    w.K = w.Y + align256(n * 160 * sizeof(float));
+    w.K = w.frame + align256(n * 9 * sizeof(double));
     w.omega = w.K + align256(n * sizeof(int32_t));
     w.mu = w.omega + align256(n * km * sizeof(double));
     w.sigma = w.mu + align256(n * km * 3 * sizeof(double));
-    w.fwd = w.sigma + align256(n * km * 6 * sizeof(double));
-    w.total = w.fwd + align256(gm_warm_forward_workspace(n_cells));
+    w.total = w.sigma + align256(n * km * 6 * sizeof(double));
     return w;
 }
 }  // namespace
@@ -391,16 +389,14 @@ int gm_compress_warm(const double* v, const double* alpha, const int64_t* cell_o
     char* w = (char*)ws;
     uint16_t* feats = (uint16_t*)(w + L.feats);
     double* frame = (double*)(w + L.frame);
-    float* Y = (float*)(w + L.Y);
     gm_init init;
     init.K = (const int32_t*)(w + L.K);
     init.omega = (const double*)(w + L.omega);
     init.mu = (const double*)(w + L.mu);
     init.sigma = (const double*)(w + L.sigma);
     if ((rc = gm_warm_features(v, alpha, cell_off, n_cells, 3, feats, frame, stream)) != GM_OK) return rc;
-    if ((rc = gm_warm_forward(model, feats, n_cells, Y, w + L.fwd, L.total - L.fwd, stream)) != GM_OK) return rc;
-    if ((rc = gm_warm_decode(Y, frame, cell_off, n_cells, o->kmax, (int32_t*)(w + L.K), (double*)(w + L.omega),
-                             (double*)(w + L.mu), (double*)(w + L.sigma), stream)) != GM_OK)
+    if ((rc = gm_warm_infer(model, feats, frame, cell_off, n_cells, o->kmax, (int32_t*)(w + L.K),
+                            (double*)(w + L.omega), (double*)(w + L.mu), (double*)(w + L.sigma), stream)) != GM_OK)
         return rc;
     return compress_run(v, alpha, cell_off, n_cells, o, nullptr, &init, out, w, (hipStream_t)stream);
 }

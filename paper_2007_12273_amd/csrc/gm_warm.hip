@@ -355,23 +355,23 @@ __global__ void k_init_params(float* w, uint64_t seed)
 // ---------------------------------------------------------------------------
 // decode: network outputs -> initial mixtures, one thread per cell
 // ---------------------------------------------------------------------------
-__global__ void k_decode3(const float* Y, const double* frame, const int64_t* off, int64_t n_cells, int kmax,
-                          int32_t* K, double* w, double* mu, double* S)
+// decode of one cell's network outputs y [NO] with its frame fr [9] (mean,
+// then the packed lower Cholesky factor of the cell covariance) into kmax
+// gm_init slots: softmax weights, slots whose expected count N p_j is not
+// above T/2 dropped (the most probable one kept if none is), the remaining
+// weights renormalised; means m + L_C mu_hat, covariances L_C L_hat L_hat^T
+// L_C^T with L_hat's diagonal exponentiated
+__device__ void decode_row(const float* y, const double* fr, double N, int kmax, int32_t& Kc, double* w, double* mu,
+                           double* S)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    const float* y = Y + (size_t)c * NO;
-    const double* fr = frame + (size_t)c * 9;
-    const double N = (double)(off[c + 1] - off[c]);
     const double halfT = 4.5;
     for (int q = 0; q < kmax; ++q) {
-        const size_t s = (size_t)c * kmax + q;
-        w[s] = 0.0;
-        for (int d = 0; d < 3; ++d) mu[s * 3 + d] = 0.0;
-        for (int d = 0; d < 6; ++d) S[s * 6 + d] = 0.0;
+        w[q] = 0.0;
+        for (int d = 0; d < 3; ++d) mu[q * 3 + d] = 0.0;
+        for (int d = 0; d < 6; ++d) S[q * 6 + d] = 0.0;
     }
     if (!(fr[3] > 0.0)) {
-        K[c] = 0;  // no frame (singular or empty cell): cold start
+        Kc = 0;  // no frame (singular or empty cell): cold start
         return;
     }
     double mx = -INFINITY;
@@ -393,15 +393,14 @@ __global__ void k_decode3(const float* Y, const double* frame, const int64_t* of
     double ws = 0.0;
     for (int q = 0; q < nk; ++q) ws += p[keep[q]];
     const double LC[3][3] = {{fr[3], 0, 0}, {fr[4], fr[5], 0}, {fr[6], fr[7], fr[8]}};
-    K[c] = nk;
+    Kc = nk;
     for (int q = 0; q < nk; ++q) {
-        const size_t s = (size_t)c * kmax + q;
         const float* o = y + keep[q] * SLOT;
-        w[s] = p[keep[q]] / ws;
+        w[q] = p[keep[q]] / ws;
         for (int d = 0; d < 3; ++d) {
             double t = fr[d];
             for (int e = 0; e <= d; ++e) t += LC[d][e] * (double)o[1 + e];
-            mu[s * 3 + d] = t;
+            mu[q * 3 + d] = t;
         }
         const double Lh[3][3] = {{exp((double)o[4]), 0, 0}, {(double)o[5], exp((double)o[6]), 0},
                                  {(double)o[7], (double)o[8], exp((double)o[9])}};
@@ -417,8 +416,104 @@ __global__ void k_decode3(const float* Y, const double* frame, const int64_t* of
             for (int jj = i; jj < 3; ++jj, ++t) {
                 double a = 0.0;
                 for (int e = 0; e < 3; ++e) a += L[i][e] * L[jj][e];
-                S[s * 6 + t] = a;
+                S[q * 6 + t] = a;
             }
+    }
+}
+
+__global__ void k_decode3(const float* Y, const double* frame, const int64_t* off, int64_t n_cells, int kmax,
+                          int32_t* K, double* w, double* mu, double* S)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const size_t s0 = (size_t)c * kmax;
+    decode_row(Y + (size_t)c * NO, frame + (size_t)c * 9, (double)(off[c + 1] - off[c]), kmax, K[c], w + s0,
+               mu + s0 * 3, S + s0 * 6);
+}
+
+// ---------------------------------------------------------------------------
+// Fused inference: the three layers and the decode for a tile of kInferRows
+// cells per 256-thread workgroup.  Activations stay in LDS (BF16 between
+// layers, FP32 network outputs); each layer's weights pass through LDS in
+// blocks of 32 input rows, stored transposed so every MFMA operand is one
+// 16-byte read.  Each 16x16 output tile accumulates over the inputs in the
+// order of k_gemm with the same MFMA, then the same bias, ReLU and BF16
+// rounding, so the outputs equal the separate launches' bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kInferRows = 32;
+constexpr int kInferThreads = 256;
+
+__global__ __launch_bounds__(kInferThreads) void k_mlp_infer(const uint16_t* X, int rows, const uint16_t* wb,
+                                                              const float* w, const double* frame, const int64_t* off,
+                                                              int kmax, int32_t* K, double* om, double* mu, double* S)
+{
+    __shared__ __align__(16) uint16_t s_a[kInferRows * NH];         // X (NFP wide), later H2 (NH wide)
+    __shared__ __align__(16) unsigned char s_hy[kInferRows * NO * 4]; // H1 (BF16), later the FP32 outputs
+    __shared__ __align__(16) uint16_t s_wt[NH * 32];                // one weight block, transposed [col][32]
+    uint16_t* s_h1 = reinterpret_cast<uint16_t*>(s_hy);
+    float* s_y = reinterpret_cast<float*>(s_hy);
+    static_assert(kInferRows * NO * 4 >= kInferRows * NH * 2, "H1 must fit the output buffer");
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r0 = blockIdx.x * kInferRows;
+    for (int t = tid; t < kInferRows * NFP / 8; t += kInferThreads) {
+        const int r = t / (NFP / 8), q = t % (NFP / 8);
+        u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r0 + r < rows) val = reinterpret_cast<const u16x8*>(X + (size_t)(r0 + r) * NFP)[q];
+        reinterpret_cast<u16x8*>(s_a + r * NFP)[q] = val;
+    }
+    // OUT[32 x N] = IN[32 x KD] W[KD x N] + bias (ReLU): a wave owns output
+    // tiles t = wave, wave + 4, ... (two row tiles by N / 16 column tiles),
+    // at most NH / 16 * 2 / 4 = 8 per wave
+    auto layer = [&](const uint16_t* in, int KD, const uint16_t* W, int N, const float* bias, bool relu,
+                     uint16_t* out16, float* out32) {
+        const int ntile = 2 * (N / 16);
+        f32x4 acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int kq = (lane >> 4) * 8;
+        for (int k0 = 0; k0 < KD; k0 += 32) {
+            __syncthreads();  // the previous block's reads (and the input writes) are done
+            for (int t = tid; t < 32 * N; t += kInferThreads) {
+                const int kk = t / N, j = t % N;
+                s_wt[j * 32 + kk] = W[(size_t)(k0 + kk) * N + j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = wave + 4 * u;
+                if (t >= ntile) break;
+                const int i0 = (t & 1) * 16, j0 = (t >> 1) * 16;
+                const u16x8 a = *reinterpret_cast<const u16x8*>(in + (i0 + (lane & 15)) * KD + k0 + kq);
+                const u16x8 b = *reinterpret_cast<const u16x8*>(s_wt + (j0 + (lane & 15)) * 32 + kq);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                 __builtin_bit_cast(bf16x8, b), acc[u], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read `in` before it is overwritten
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = wave + 4 * u;
+            if (t >= ntile) break;
+            const int i0 = (t & 1) * 16, j = (t >> 1) * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + (lane >> 4) * 4 + r;
+                float x = acc[u][r] + bias[j];
+                if (relu) x = x > 0.f ? x : 0.f;
+                if (out16) out16[i * N + j] = f2bf(x);
+                if (out32) out32[i * N + j] = x;
+            }
+        }
+    };
+    layer(s_a, NFP, wb + OFF_W1, NH, w + OFF_B1, true, s_h1, nullptr);
+    layer(s_h1, NH, wb + OFF_W2, NH, w + OFF_B2, true, s_a, nullptr);
+    layer(s_a, NH, wb + OFF_W3, NO, w + OFF_B3, false, nullptr, s_y);
+    __syncthreads();
+    if (tid < kInferRows && r0 + tid < rows) {
+        const int64_t c = r0 + tid;
+        const size_t s0 = (size_t)c * kmax;
+        decode_row(s_y + tid * NO, frame + (size_t)c * 9, (double)(off[c + 1] - off[c]), kmax, K[c], om + s0,
+                   mu + s0 * 3, S + s0 * 6);
     }
 }
 
@@ -747,6 +842,18 @@ size_t gm_warm_forward_workspace(int64_t n_rows)
 {
     if (n_rows < 0) return 0;
     return al256((size_t)n_rows * gm::NH * 2) * 2;
+}
+
+int gm_warm_infer(const gm_warm* m, const uint16_t* feats, const double* frame, const int64_t* cell_off,
+                  int64_t n_cells, int32_t kmax, int32_t* K, double* omega, double* mu, double* sigma, void* stream)
+{
+    if (!m || n_cells < 0 || n_cells > 0x7fffffff || kmax < 1 || kmax > 16) return GM_EINVAL;
+    if (n_cells == 0) return GM_OK;
+    if (!feats || !frame || !cell_off || !K || !omega || !mu || !sigma) return GM_EINVAL;
+    const unsigned nb = (unsigned)((n_cells + gm::kInferRows - 1) / gm::kInferRows);
+    hipLaunchKernelGGL(gm::k_mlp_infer, dim3(nb), dim3(gm::kInferThreads), 0, (hipStream_t)stream, feats,
+                       (int)n_cells, m->wb, m->w, frame, cell_off, kmax, K, omega, mu, sigma);
+    return launch_ok();
 }
 
 int gm_warm_decode(const float* Y, const double* frame, const int64_t* cell_off, int64_t n_cells, int32_t kmax,

@@ -425,3 +425,30 @@ def test_unusable_supplied_start_starts_cold_on_gpu():
         for k in ("K", "sweeps", "visits", "omega", "mu", "sigma", "L_pen", "L_final"):
             assert np.array_equal(g[k][c], cold[k][c]), (c, k)
         assert g["status"][c] == cold["status"][c] | FALLBACK
+
+
+def test_fused_inference_equals_forward_and_decode():
+    """gm_warm_infer (three layers and the decode in one launch, 32 cells per
+    workgroup) gives the mixtures of gm_warm_forward followed by
+    gm_warm_decode bit for bit, on a batch that is not a multiple of the
+    tile, with trained and with seeded weights."""
+    api = _api()
+    d = _subset(synth.make("weibel_3v"), 1000)
+    v, a, off = to_gpu(d)
+    f, fr = api.warm_features(v, a, off)
+    from paper_2007_12273_amd import warm as warmlib
+    tr = _subset(synth.make("weibel_3v", seed=5003), 1024)
+    feats, targs = warmlib.training_set([tr], 16, seed=2003, device=dev())
+    for trained in (False, True):
+        m = api.WarmStart(16, batch=256, seed=11, device=dev())
+        if trained:
+            warmlib.train(m, feats, targs, epochs=4)
+        ref = host(api.warm_decode(m.forward(f), fr, off, 16))
+        out = {"K": torch.empty(1000, dtype=torch.int32, device=dev()),
+               "omega": torch.empty(1000, 16, dtype=torch.float64, device=dev()),
+               "mu": torch.empty(1000, 16, 3, dtype=torch.float64, device=dev()),
+               "sigma": torch.empty(1000, 16, 6, dtype=torch.float64, device=dev())}
+        got = host(m.infer(f, fr, off, out))
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (trained, k)
+        m.close()
