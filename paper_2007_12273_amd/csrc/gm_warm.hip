@@ -167,8 +167,12 @@ __global__ __launch_bounds__(kFeatThreads) void k_features3(const double* v, con
 // ---------------------------------------------------------------------------
 // BF16 GEMM on MFMA 16x16x32: one wave per 16x16 output tile, four waves per
 // workgroup (a 32x32 block tile).  A(i,k) = A[i*sa_i + k*sa_k],
-// B(k,j) = B[k*sb_k + j*sb_j].  Epilogue: + bias[j], ReLU, mask (keep where
-// mask(i,j) > 0), then FP32 and/or BF16 stores.
+// B(k,j) = B[k*sb_k + j*sb_j].  Each 32-wide step of k stages the block's
+// A and B slices through LDS, loaded along whichever index is contiguous in
+// memory (the transposed operands of the backward products included) and
+// stored k-contiguous, so every MFMA operand is one 16-byte LDS read.
+// Epilogue: + bias[j], ReLU, mask (keep where mask(i,j) > 0), then FP32
+// and/or BF16 stores.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
     const uint16_t* A;
@@ -186,27 +190,66 @@ struct GemmArgs {
     int64_t ldc16;
 };
 
+constexpr int kGemmPad = 40;  // LDS row length of a staged slice (32 values + 8 of padding)
+
+// 32 x 32 slice of a strided matrix into s[r][k] (row r, k contiguous):
+// M(r, k) = P[r * s_r + k * s_k], rows r0.., columns k0.., zero outside
+// [0, nr) x [0, nk).  Where one stride is 1 and the eight values a thread
+// takes are inside the matrix and 16-byte aligned, they come in one vector
+// load (128 threads); otherwise element by element.
+__device__ __forceinline__ void stage_slice(const uint16_t* P, int64_t s_r, int64_t s_k, int r0, int k0, int nr,
+                                            int nk, uint16_t (*s)[kGemmPad])
+{
+    const int t = threadIdx.x & 127;
+    const bool kfast = s_k == 1;
+    // this thread's run of eight along the contiguous index
+    const int run = t & 3, other = t >> 2;        // 4 runs of 8 along the fast index, 32 along the other
+    const int r = kfast ? other : run * 8;        // first row of the run
+    const int k = kfast ? run * 8 : other;        // first column of the run
+    const int gr = r0 + r, gk = k0 + k;
+    const int64_t base = (int64_t)gr * s_r + (int64_t)gk * s_k;
+    const bool inside = kfast ? (gr < nr && gk + 8 <= nk) : (gk < nk && gr + 8 <= nr);
+    const bool vec = (kfast || s_r == 1) && inside && ((reinterpret_cast<uintptr_t>(P + base) & 15) == 0);
+    u16x8 val;
+    if (vec) {
+        val = *reinterpret_cast<const u16x8*>(P + base);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int rr = kfast ? gr : gr + e, kk = kfast ? gk + e : gk;
+            val[e] = (rr < nr && kk < nk) ? P[(int64_t)rr * s_r + (int64_t)kk * s_k] : (uint16_t)0;
+        }
+    }
+    if (kfast) {
+        *reinterpret_cast<u16x8*>(&s[r][k]) = val;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[r + e][k] = val[e];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
+    __shared__ __align__(16) uint16_t sA[32][kGemmPad];
+    __shared__ __align__(16) uint16_t sB[32][kGemmPad];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i0 = blockIdx.x * 32 + (wave >> 1) * 16;
-    const int j0 = blockIdx.y * 32 + (wave & 1) * 16;
-    const int ia = i0 + (lane & 15);
-    const int jb = j0 + (lane & 15);
+    const int bi = blockIdx.x * 32, bj = blockIdx.y * 32;
+    const int ti = (wave >> 1) * 16, tj = (wave & 1) * 16;
     const int kq = (lane >> 4) * 8;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < g.K; k0 += 32) {
-        u16x8 a, b;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + kq + e;
-            a[e] = (ia < g.M && k < g.K) ? g.A[(int64_t)ia * g.sa_i + (int64_t)k * g.sa_k] : (unsigned short)0;
-            b[e] = (jb < g.N && k < g.K) ? g.B[(int64_t)k * g.sb_k + (int64_t)jb * g.sb_j] : (unsigned short)0;
-        }
+        __syncthreads();  // the previous step's operand reads are done
+        if (threadIdx.x < 128)
+            stage_slice(g.A, g.sa_i, g.sa_k, bi, k0, g.M, g.K, sA);
+        else
+            stage_slice(g.B, g.sb_j, g.sb_k, bj, k0, g.N, g.K, sB);
+        __syncthreads();
+        const u16x8 a = *reinterpret_cast<const u16x8*>(&sA[ti + (lane & 15)][kq]);
+        const u16x8 b = *reinterpret_cast<const u16x8*>(&sB[tj + (lane & 15)][kq]);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
                                                       acc, 0, 0, 0);
     }
-    const int j = j0 + (lane & 15);
+    const int i0 = bi + ti, j = bj + tj + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = i0 + (lane >> 4) * 4 + r;
