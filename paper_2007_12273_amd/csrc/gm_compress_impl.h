@@ -581,15 +581,20 @@ __device__ __forceinline__ double sqrt_det(const double* C)
 // threads compute the identical M-step, so a wave can publish an update to
 // its copy without waiting for the others.  The only workgroup barrier per
 // component update is the one inside the cross-wave reduction.
-// Standard FP32 builds are held to three waves per SIMD (at most 168 VGPRs)
-// so that a CU holds two cells of up to five waves each; the FP64 builds keep
-// the whole register file (two waves per SIMD).
-template <typename R, bool LEAN>
-constexpr int em_min_waves_per_simd() { return (LEAN || !std::is_same<R, float>::value) ? 1 : 3; }
+// The standard FP32 build with one register-resident particle per thread is
+// held to three waves per SIMD (at most 168 VGPRs, which it fits without
+// spilling): more of its small cells per CU.  The other builds keep the
+// register file they need: held to 168 VGPRs they spill inside the update
+// loop (measured: 4x the EM phase's algorithmic HBM bytes).
+template <typename R, bool LEAN, int P, bool STORE_E>
+constexpr int em_min_waves_per_simd()
+{
+    return (!LEAN && std::is_same<R, float>::value && STORE_E && P == 1) ? 3 : 1;
+}
 
 template <int D, int KMAX, int P, bool STORE_E, typename R, bool LEAN>
-__global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_waves_per_simd<R, LEAN>())) void k_em(
-    CompressArgs A_in)
+__global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_waves_per_simd<R, LEAN, P, STORE_E>()))
+void k_em(CompressArgs A_in)
 {
     constexpr int MAXW = em_max_waves(LEAN);
     constexpr int NT = ntri(D);
@@ -618,12 +623,16 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_wave
     int par_d = 0, par_r = 0;
     CompState<R, D>* comp = compw[wid];
 
+    // The first cell is claimed before the loop: a workgroup that finds the
+    // queue empty leaves before the loop's invariants are set up (a build
+    // that fills the register file spills them to scratch, a write per lane
+    // of every workgroup of the persistent grid).
+    if (tid == 0) s_idx = atomicAdd(&A.plan[PLAN_QUEUE + bucket], 1);
+    __syncthreads();
+    int idx = s_idx;
+    __syncthreads();
+    if (idx >= count) return;
     for (;;) {
-        if (tid == 0) s_idx = atomicAdd(&A.plan[PLAN_QUEUE + bucket], 1);
-        __syncthreads();
-        const int idx = s_idx;
-        __syncthreads();
-        if (idx >= count) break;
         const int c = A.list[base + idx];
         const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
         const int n = ci->n;
@@ -1157,6 +1166,11 @@ __global__ __launch_bounds__(LEAN ? kEmLeanThreads : kEmMaxThreads, (em_min_wave
             A.out.status[c] = status;
         }
         __syncthreads();
+        if (tid == 0) s_idx = atomicAdd(&A.plan[PLAN_QUEUE + bucket], 1);
+        __syncthreads();
+        idx = s_idx;
+        __syncthreads();
+        if (idx >= count) break;
     }
 }
 

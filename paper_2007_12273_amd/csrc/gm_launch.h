@@ -48,10 +48,11 @@ constexpr int kMaxCellParticles = 8192;
 
 // Launch variants a bucket can run with (the autotuner picks among them):
 // particles per thread, whether the density terms stay in registers, and
-// the build: standard (workgroups of up to 512 threads; FP32 at most 168
-// VGPRs per lane, three waves per SIMD; FP64 up to 256, two) or lean (up to
-// 1024 threads, at most 128 VGPRs, four waves per SIMD: more cells in
-// flight per CU, and 16-wave workgroups for the largest cells).  Lean builds exist for FP32 iterations
+// the build: standard (workgroups of up to 512 threads, up to 256 VGPRs per
+// lane, two waves per SIMD; three for FP32 with one register-resident
+// particle per thread) or lean (up to 1024 threads, at most 128 VGPRs, four
+// waves per SIMD: more cells in flight per CU, and 16-wave workgroups for
+// the largest cells).  Lean builds exist for FP32 iterations
 // only.  A variant fits a bucket when 64 * waves * per_thread >= max_n with
 // waves = ceil(max_n / (64 * per_thread)) <= the build's waves.
 // Register-resident densities with 8 particles per thread are built for
