@@ -30,6 +30,20 @@ struct u64x4 {
     uint64_t x, y, z, w;
 };
 
+// Full 128-bit product of two 64-bit words from four 32 x 32 + 64 -> 64
+// multiply-adds (v_mad_u64_u32), each partial product's carry folded into
+// the next one's addend: hi:lo = m * x exactly.
+__device__ __forceinline__ void mul_64x64_128(uint64_t m, uint64_t x, uint64_t& hi, uint64_t& lo)
+{
+    const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32), x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+    const uint64_t t = (uint64_t)m0 * x0;
+    const uint64_t u = (uint64_t)m1 * x0 + (t >> 32);       // < 2^64: (2^32 - 1)^2 + 2^32 - 1
+    const uint64_t w = (uint64_t)m0 * x1 + (uint32_t)u;
+    const uint64_t y = (uint64_t)m1 * x1 + (u >> 32);
+    hi = y + (w >> 32);
+    lo = (w << 32) | (uint32_t)t;
+}
+
 __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                                uint64_t k1)
 {
@@ -37,8 +51,9 @@ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
     const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_64x64_128(M0, c0, hi0, lo0);
+        mul_64x64_128(M1, c2, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0;
         const uint64_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;

@@ -5,18 +5,20 @@
 // particles whose weights changed after sampling (the Gauss'-law correction
 // of Sec. 2.4.1).
 //
-// One workgroup per cell.  Every particle is generated once from its own
-// Philox counter; up to RP particles per thread stay in registers between
-// the sample-moment reduction and the projected write, so the output is
-// written exactly once.  Cells larger than RP * blockDim regenerate their
-// particles in a second pass instead of re-reading them.
+// A workgroup of four waves serves four consecutive cells: each cell of at
+// most 512 particles is drawn by one wave on its own (no cross-wave
+// reduction, no barrier), the larger ones afterwards by the whole
+// workgroup, one after another.  Every particle is generated once from its
+// own Philox counter and written unprojected; after the sample-moment
+// reduction each thread reads back the velocities it wrote (from L2: a
+// cell's output is a few ten KB) and overwrites them with their projected
+// image, so HBM sees each output byte written once.
 #include "gm_device.h"
 #include "gm_launch.h"
 
 namespace gm {
 
 constexpr int kReconThreads = 256;
-constexpr int kReconRegs = 8;
 
 // Particle i of cell c: uniform j is word j % 4 of Philox block j / 4 with
 // counter (i, c, j / 4, 0) and key (seed, "RECO").  Uniform 0 picks the
@@ -49,9 +51,10 @@ __device__ __forceinline__ void draw_particle(uint64_t seed, int c, int64_t i, i
 #pragma unroll
     for (int pr = 0; pr < NPAIR; ++pr) {
         const double r = sqrt(-2.0 * log(1.0 - u[1 + 2 * pr]));
-        const double th = 6.283185307179586476925286766559 * u[2 + 2 * pr];
+        // angle 2 pi u: sincospi(2u) takes the exact argument 2u (no
+        // reduction by a rounded pi)
         double sn, cs;
-        sincos(th, &sn, &cs);
+        sincospi(2.0 * u[2 + 2 * pr], &sn, &cs);
         z[2 * pr] = r * cs;
         z[2 * pr + 1] = r * sn;
     }
@@ -226,55 +229,59 @@ struct Projection {
     }
 };
 
-// One workgroup per cell: draw the cell's n' particles, reduce their sums,
-// then write the projected velocities (TENSOR: full second moment; else
-// Lemons' scalar form).
-template <int D, bool TENSOR>
-__global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
+constexpr int kWaveCell = 512;  // largest cell drawn by one wave (8 particles per lane)
+
+// Draw cell c's n' particles, reduce their sums, then write the projected
+// velocities (TENSOR: full second moment; else Lemons' scalar form).  WAVE:
+// the 64 lanes of one wave (t = lane) with the wave's own tables; else the
+// whole workgroup (t = thread).  Statuses: LEMONS_SKIPPED when the
+// projection has no solution, DEGENERATE when a covariance does not factor
+// (its component is sampled at its mean) or K is out of range (zero output).
+template <int D, bool TENSOR, bool WAVE>
+__device__ __forceinline__ void recon_cell(const ReconArgs& A, int c, int64_t o0, int64_t n, int t,
+                                           double (*s_mu)[D], double (*s_L)[ntri(D)], double* s_cum, int* s_bad,
+                                           double* red, int& par)
 {
     constexpr int NT = ntri(D);
-    constexpr int KM = 16;
+    constexpr int G = WAVE ? 64 : kReconThreads;
     using Sums = SampleSums<D, TENSOR>;
-    __shared__ double s_mu[KM][D], s_L[KM][NT], s_cum[KM];
-    __shared__ double red[2 * kMaxWaves * Sums::NA];
-    __shared__ int s_bad;
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int nthreads = blockDim.x;
-    const int nwaves = nthreads >> 6;
-    int par = 0;
-    const int64_t o0 = A.out_off[c];
-    const int64_t n = A.out_off[c + 1] - o0;
+    auto sync = [] {
+        if constexpr (WAVE) {
+            // LDS operations of one wave complete in order; the fence keeps
+            // the compiler from moving them across
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
     const int kmax = A.kmax;
     const int K = A.K[c];
     const int dx = A.dx;
-    if (n <= 0) {
-        if (tid == 0) A.status[c] = 0;
-        return;
-    }
     if (K < 1 || K > kmax) {
-        for (int64_t i = tid; i < n; i += nthreads) {
+        for (int64_t i = t; i < n; i += G) {
             for (int d = 0; d < D; ++d) A.v_out[(o0 + i) * D + d] = 0.0;
             A.w_out[o0 + i] = 0.0;
             for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = 0.0;
         }
-        if (tid == 0) A.status[c] = GM_ST_DEGENERATE;
+        if (t == 0) A.status[c] = GM_ST_DEGENERATE;
         return;
     }
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    if (tid < K) {
-        const size_t s = (size_t)c * kmax + tid;
+    if (t == 0) *s_bad = 0;
+    sync();
+    if (t < K) {
+        const size_t s = (size_t)c * kmax + t;
         double S[NT], L[NT];
         for (int q = 0; q < NT; ++q) S[q] = A.sigma[s * NT + q];
         if (!chol<D, double>(S, L)) {
             for (int q = 0; q < NT; ++q) L[q] = 0.0;  // sample the mean only
-            s_bad = 1;
+            *s_bad = 1;
         }
-        for (int q = 0; q < NT; ++q) s_L[tid][q] = L[q];
-        for (int d = 0; d < D; ++d) s_mu[tid][d] = A.mu[s * D + d];
+        for (int q = 0; q < NT; ++q) s_L[t][q] = L[q];
+        for (int d = 0; d < D; ++d) s_mu[t][d] = A.mu[s * D + d];
     }
-    if (tid == 0) {
+    if (t == 0) {
         double run = 0.0;
         for (int k = 0; k < K; ++k) {
             run += A.omega[(size_t)c * kmax + k];
@@ -282,56 +289,86 @@ __global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A)
         }
         s_cum[K - 1] = 1.0;
     }
-    __syncthreads();
+    sync();
     // targets from the compress moments record: W, P = sum alpha v, S = sum
     // alpha v v^T (the scalar projection takes E = tr(S) / 2)
     const double* tg = A.target + (size_t)c * nmom(D);
     const double wp = tg[0] / (double)n;
-    const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
 
-    double vr[kReconRegs][D];
     Sums sums;
     sums.zero();
-    // pass 1: draw, write weights and positions, reduce the sample's sums
-    if (in_regs) {
+    // pass 1: draw, write the particles (velocities unprojected), reduce the
+    // sample's sums
+    for (int64_t i = t; i < n; i += G) {
+        double v[D], xp[3];
+        draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, v, xp);
 #pragma unroll
-        for (int j = 0; j < kReconRegs; ++j) {
-            const int64_t i = tid + (int64_t)j * nthreads;
-            if (i < n) {
-                double xp[3];
-                draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, vr[j], xp);
-                A.w_out[o0 + i] = wp;
-                for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
-                sums.add(vr[j], wp);
-            }
-        }
-    } else {
-        for (int64_t i = tid; i < n; i += nthreads) {
-            double v[D], xp[3];
-            draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, dx, v, xp);
-            A.w_out[o0 + i] = wp;
-            for (int d = 0; d < dx; ++d) A.x_out[(o0 + i) * dx + d] = xp[d];
-            sums.add(v, wp);
-        }
+        for (int d = 0; d < D; ++d) A.v_out[(o0 + i) * D + d] = v[d];
+        A.w_out[o0 + i] = wp;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (d < dx) A.x_out[(o0 + i) * dx + d] = xp[d];
+        sums.add(v, wp);
     }
-    block_sum<Sums::NA>(sums.acc, red, par, nwaves);
+    if constexpr (WAVE) {
+#pragma unroll
+        for (int q = 0; q < Sums::NA; ++q) sums.acc[q] = wave_sum(sums.acc[q]);
+    } else {
+        block_sum<Sums::NA>(sums.acc, red, par, G >> 6);
+    }
     Projection<D, TENSOR> pr;
     pr.setup(sums.acc, tg);
-    // pass 2: projected velocities
-    if (in_regs) {
+    // pass 2: every thread reads back the velocities it wrote (a cell's
+    // particles are still in L2) and writes their projected image
+    for (int64_t i = t; i < n; i += G) {
+        double v[D];
 #pragma unroll
-        for (int j = 0; j < kReconRegs; ++j) {
-            const int64_t i = tid + (int64_t)j * nthreads;
-            if (i < n) pr.write(vr[j], A.v_out + (o0 + i) * D);
-        }
-    } else {
-        for (int64_t i = tid; i < n; i += nthreads) {
-            double v[D], xp[3];
-            draw_particle<D>(A.seed, c, i, K, s_cum, s_mu, s_L, 0, v, xp);
-            pr.write(v, A.v_out + (o0 + i) * D);
+        for (int d = 0; d < D; ++d) v[d] = A.v_out[(o0 + i) * D + d];
+        pr.write(v, A.v_out + (o0 + i) * D);
+    }
+    if (t == 0) A.status[c] = (pr.ok ? 0 : GM_ST_LEMONS_SKIPPED) | (*s_bad ? GM_ST_DEGENERATE : 0);
+}
+
+// Workgroup b serves cells 4b .. 4b + 3: first each wave draws its own cell
+// if that holds at most kWaveCell particles, then the whole workgroup draws
+// the others in order (empty cells get status 0 and no output).
+template <int D, bool TENSOR>
+__global__ __launch_bounds__(kReconThreads) void k_reconstruct(ReconArgs A, int64_t n_cells)
+{
+    constexpr int NT = ntri(D);
+    constexpr int KM = 16;
+    constexpr int NW = kReconThreads / 64;
+    using Sums = SampleSums<D, TENSOR>;
+    __shared__ double s_mu[NW][KM][D], s_L[NW][KM][NT], s_cum[NW][KM];
+    __shared__ double red[2 * kMaxWaves * Sums::NA];
+    __shared__ int s_bad[NW];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    int par = 0;
+    const int64_t cb = (int64_t)blockIdx.x * NW;
+    {
+        const int64_t c = cb + wid;
+        if (c < n_cells) {
+            const int64_t o0 = A.out_off[c];
+            const int64_t n = A.out_off[c + 1] - o0;
+            if (n <= 0) {
+                if (lane == 0) A.status[c] = 0;
+            } else if (n <= kWaveCell) {
+                recon_cell<D, TENSOR, true>(A, (int)c, o0, n, lane, s_mu[wid], s_L[wid], s_cum[wid], &s_bad[wid],
+                                            nullptr, par);
+            }
         }
     }
-    if (tid == 0) A.status[c] = (pr.ok ? 0 : GM_ST_LEMONS_SKIPPED) | (s_bad ? GM_ST_DEGENERATE : 0);
+#pragma unroll 1
+    for (int j = 0; j < NW; ++j) {
+        const int64_t c = cb + j;
+        if (c >= n_cells) break;
+        const int64_t o0 = A.out_off[c];
+        const int64_t n = A.out_off[c + 1] - o0;
+        if (n <= kWaveCell) continue;
+        __syncthreads();  // the tables of wave 0 are free
+        recon_cell<D, TENSOR, false>(A, (int)c, o0, n, tid, s_mu[0], s_L[0], s_cum[0], &s_bad[0], red, par);
+    }
 }
 
 // Projection of given particles (v, w) of each cell towards the cell's
@@ -352,45 +389,26 @@ __global__ __launch_bounds__(kReconThreads) void k_project(ProjArgs A)
         if (tid == 0) A.status[c] = 0;
         return;
     }
-    const bool in_regs = n <= (int64_t)kReconRegs * nthreads;
-    double vr[kReconRegs][D];
     Sums sums;
     sums.zero();
     auto load = [&](int64_t i, double (&v)[D]) {
 #pragma unroll
         for (int d = 0; d < D; ++d) v[d] = A.v[(o0 + i) * D + d];
     };
-    if (in_regs) {
-#pragma unroll
-        for (int j = 0; j < kReconRegs; ++j) {
-            const int64_t i = tid + (int64_t)j * nthreads;
-            if (i < n) {
-                load(i, vr[j]);
-                sums.add(vr[j], A.w[o0 + i]);
-            }
-        }
-    } else {
-        for (int64_t i = tid; i < n; i += nthreads) {
-            double v[D];
-            load(i, v);
-            sums.add(v, A.w[o0 + i]);
-        }
+    for (int64_t i = tid; i < n; i += nthreads) {
+        double v[D];
+        load(i, v);
+        sums.add(v, A.w[o0 + i]);
     }
     block_sum<Sums::NA>(sums.acc, red, par, nthreads >> 6);
     Projection<D, TENSOR> pr;
     pr.setup(sums.acc, A.moments + (size_t)c * nmom(D));
-    if (in_regs) {
-#pragma unroll
-        for (int j = 0; j < kReconRegs; ++j) {
-            const int64_t i = tid + (int64_t)j * nthreads;
-            if (i < n) pr.write(vr[j], A.v_out + (o0 + i) * D);
-        }
-    } else {
-        for (int64_t i = tid; i < n; i += nthreads) {
-            double v[D];
-            load(i, v);
-            pr.write(v, A.v_out + (o0 + i) * D);
-        }
+    // second read of the same particles (from L2 for cells of up to a few
+    // ten thousand particles)
+    for (int64_t i = tid; i < n; i += nthreads) {
+        double v[D];
+        load(i, v);
+        pr.write(v, A.v_out + (o0 + i) * D);
     }
     if (tid == 0) A.status[c] = pr.ok ? 0 : GM_ST_LEMONS_SKIPPED;
 }
@@ -398,17 +416,18 @@ __global__ __launch_bounds__(kReconThreads) void k_project(ProjArgs A)
 int launch_reconstruct(const ReconArgs& a, int64_t n_cells, hipStream_t st)
 {
     if (n_cells == 0) return 0;
-    const dim3 grid((unsigned)n_cells), block(kReconThreads);
+    constexpr int NW = kReconThreads / 64;
+    const dim3 grid((unsigned)((n_cells + NW - 1) / NW)), block(kReconThreads);
     if (a.D == 1) {
         if (a.tensor)
-            hipLaunchKernelGGL((k_reconstruct<1, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_reconstruct<1, true>), grid, block, 0, st, a, n_cells);
         else
-            hipLaunchKernelGGL((k_reconstruct<1, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_reconstruct<1, false>), grid, block, 0, st, a, n_cells);
     } else {
         if (a.tensor)
-            hipLaunchKernelGGL((k_reconstruct<3, true>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_reconstruct<3, true>), grid, block, 0, st, a, n_cells);
         else
-            hipLaunchKernelGGL((k_reconstruct<3, false>), grid, block, 0, st, a);
+            hipLaunchKernelGGL((k_reconstruct<3, false>), grid, block, 0, st, a, n_cells);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

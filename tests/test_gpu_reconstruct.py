@@ -113,3 +113,47 @@ def test_tensor_reconstruct_matches_oracle(name, nc, dx):
         assert np.abs((w[:, None] * v).sum(0) - m[1:1 + D]).max() <= 1e-12 * np.sqrt(m[0] * np.abs(S).max())
         Sv = (w[:, None, None] * v[:, :, None] * v[:, None, :]).sum(0)[iu]
         assert np.abs(Sv - S).max() <= 1e-12 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("projection", ["scalar", "tensor"])
+def test_reconstruct_cell_sizes_around_the_wave_limit(projection):
+    """Cells drawn by one wave (at most 512 particles) and by the whole
+    workgroup (more) side by side in the same group of four cells, empty
+    cells among them, and a cell count that is not a multiple of four:
+    every particle within 1e-12 of the oracle's, statuses equal, and the
+    projected sample's moments equal to the record's."""
+    from paper_2007_12273_amd import api
+    D, dx = 3, 2
+    counts = np.array([0, 1, 64, 65, 511, 512, 513, 2048, 2049, 0, 5000, 7, 300], np.int64)
+    nc = len(counts)
+    d = synth.make("weibel_3v")
+    off = d["cell_off"]
+    sub = dict(v=d["v"][:off[nc]], alpha=d["alpha"][:off[nc]], cell_off=off[:nc + 1])
+    mix = oracle.compress(sub["v"], sub["alpha"], sub["cell_off"], kmax=16, seed=1, max_sweeps=25)
+    out_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    if projection == "tensor":
+        o = oracle.reconstruct_tensor(mix["K"], mix["omega"], mix["mu"], mix["sigma"], out_off, mix["moments"], D,
+                                      dx, seed=5005)
+    else:
+        o = oracle.reconstruct(mix["K"], mix["omega"], mix["mu"], mix["sigma"], out_off,
+                               oracle.targets_from_moments(mix["moments"], D), D, dx, seed=5005)
+    g = dev()
+    t = lambda x, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(x)).to(g).to(dt)
+    r = host(api.reconstruct(t(mix["K"], torch.int32), t(mix["omega"]), t(mix["mu"]), t(mix["sigma"]),
+                             t(out_off, torch.int64), t(mix["moments"]), D, dx, 5005, projection=projection))
+    assert np.array_equal(r["status"], o["status"])
+    assert np.array_equal(r["x"], o["x"])
+    np.testing.assert_allclose(r["w"], o["w"], rtol=1e-15, atol=0)
+    tg = oracle.targets_from_moments(mix["moments"], D)
+    scale = np.sqrt(np.maximum(tg[:, 1 + D] / tg[:, 0], 1e-300))
+    cell_of = np.repeat(np.arange(nc), counts)
+    err = np.abs(r["v"] - o["v"]).max(axis=1) / scale[cell_of]
+    assert err.max() < 1e-12, err.max()
+    for c in range(nc):
+        if counts[c] < 2:
+            continue
+        sl = slice(out_off[c], out_off[c + 1])
+        w, v = r["w"][sl], r["v"][sl]
+        m = mix["moments"][c]
+        assert abs(w.sum() - m[0]) <= 1e-13 * m[0]
+        assert np.abs((w[:, None] * v).sum(0) - m[1:1 + D]).max() <= 1e-12 * np.sqrt(m[0] * np.abs(m[1 + D:]).max())
