@@ -87,7 +87,10 @@ struct CompressArgs {
     gm_mix out;
 };
 
-enum { PLAN_COUNT = 0, PLAN_BASE = 16, PLAN_CURSOR = 32, PLAN_QUEUE = 48, PLAN_SIZE = 64 };
+// PLAN_LEVEL: per bucket, kPlanLevels counters of its cells by size level
+// (counts in k_moments, turned into list positions by k_plan_scan)
+constexpr int kPlanLevels = 16;
+enum { PLAN_COUNT = 0, PLAN_BASE = 16, PLAN_QUEUE = 32, PLAN_LEVEL = 48, PLAN_SIZE = 48 + 16 * kPlanLevels };
 
 // standard EM (gm_std.hip)
 constexpr int kStdAaMax = 5;  // largest Anderson memory
@@ -115,6 +118,20 @@ __host__ __device__ inline int bucket_of(int kmax_tpl, int n)
     for (int b = 0; b < kNumBuckets; ++b)
         if (n <= bucket_cfg(kmax_tpl, b).max_n) return b;
     return -1;
+}
+
+// Size level of an n-particle cell within its bucket's range: 0 for the
+// largest cells, kPlanLevels - 1 for the smallest.  A bucket's queue hands
+// out its cells level by level, largest first: the fit's cost grows with
+// the cell's size (more particles per update and, on these inputs, more
+// sweeps), so the longest fits start first and do not trail the phase.
+__host__ __device__ inline int size_level(int kmax_tpl, int b, int n)
+{
+    if (b < 0 || b >= kNumBuckets) return 0;
+    const int hi = bucket_cfg(kmax_tpl, b).max_n;
+    const int lo = b == 0 ? 1 : bucket_cfg(kmax_tpl, b - 1).max_n + 1;
+    const int l = (int)((int64_t)(hi - n) * kPlanLevels / (hi - lo + 1));
+    return l < 0 ? 0 : (l >= kPlanLevels ? kPlanLevels - 1 : l);
 }
 
 // ===========================================================================
@@ -213,7 +230,12 @@ __global__ __launch_bounds__(64 * kMomCellsPerBlock) void k_moments(CompressArgs
         ci->n = n;
         const bool big = n > kMaxCellParticles;
         ci->kind = closed ? CELL_CLOSED : (big ? CELL_BIG : CELL_EM);
-        if (!closed) atomicAdd(&A.plan[PLAN_COUNT + (big ? kNumBuckets : bucket_of(A.kmax <= 8 ? 8 : 16, n))], 1);
+        if (!closed) {
+            const int kt = A.kmax <= 8 ? 8 : 16;
+            const int b = big ? kNumBuckets : bucket_of(kt, n);
+            atomicAdd(&A.plan[PLAN_COUNT + b], 1);
+            atomicAdd(&A.plan[PLAN_LEVEL + b * kPlanLevels + size_level(kt, b, n)], 1);
+        }
     }
     if (closed) return;
     // cold start: min(kmax, n, floor(N/T)) distinct particles by a partial
@@ -268,43 +290,53 @@ static __global__ void k_plan_scan(int32_t* plan)
     int base = 0;
     for (int b = 0; b <= kNumBuckets; ++b) {
         plan[PLAN_BASE + b] = base;
-        plan[PLAN_CURSOR + b] = 0;
         plan[PLAN_QUEUE + b] = 0;
+        // level counts -> first list position of each level
+        int pos = base;
+        for (int l = 0; l < kPlanLevels; ++l) {
+            const int cnt = plan[PLAN_LEVEL + b * kPlanLevels + l];
+            plan[PLAN_LEVEL + b * kPlanLevels + l] = pos;
+            pos += cnt;
+        }
         base += plan[PLAN_COUNT + b];
     }
 }
 
-// EM cells into their buckets: per wave, one atomic per distinct bucket
-// among its lanes (a cursor add of the group's size), and each lane's slot
-// is its rank within the group
+// EM cells into their buckets, level by level: per wave, one atomic per
+// distinct (bucket, size level) among its lanes (an add of the group's size
+// to that level's list position), and each lane's slot is its rank within
+// the group
 template <int D>
 __global__ void k_plan_scatter(CompressArgs A)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    int b = -1;
+    int key = -1;
     if (c < A.n_cells) {
         const CellInfo<D>* ci = static_cast<const CellInfo<D>*>(A.cells) + c;
-        if (ci->kind == CELL_EM) b = bucket_of(A.kmax <= 8 ? 8 : 16, ci->n);
+        const int kt = A.kmax <= 8 ? 8 : 16;
+        int b = -1;
+        if (ci->kind == CELL_EM) b = bucket_of(kt, ci->n);
         else if (ci->kind == CELL_BIG) b = kNumBuckets;
+        if (b >= 0) key = b * kPlanLevels + size_level(kt, b, ci->n);
     }
-    uint64_t todo = __builtin_amdgcn_ballot_w64(b >= 0);
+    uint64_t todo = __builtin_amdgcn_ballot_w64(key >= 0);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     while (todo) {
         const int leader = __builtin_ctzll(todo);
-        const int bl = __builtin_amdgcn_readlane(b, leader);
-        const uint64_t group = __builtin_amdgcn_ballot_w64(b == bl);
+        const int kl = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t group = __builtin_amdgcn_ballot_w64(key == kl);
         int first = 0;
-        if (lane == leader) first = atomicAdd(&A.plan[PLAN_CURSOR + bl], __builtin_popcountll(group));
+        if (lane == leader) first = atomicAdd(&A.plan[PLAN_LEVEL + kl], __builtin_popcountll(group));
         first = __builtin_amdgcn_readlane(first, leader);
-        if (b == bl) A.list[A.plan[PLAN_BASE + bl] + first + __builtin_popcountll(group & below)] = (int32_t)c;
+        if (key == kl) A.list[first + __builtin_popcountll(group & below)] = (int32_t)c;
         todo &= ~group;
     }
 }
 
 static __global__ void k_plan_reset(int32_t* plan)
 {
-    if (threadIdx.x < PLAN_SIZE) plan[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < PLAN_SIZE; i += blockDim.x) plan[i] = 0;
 }
 
 // rewind every bucket's work queue (the autotuner reruns the EM launches)
