@@ -1535,24 +1535,27 @@ __global__ __launch_bounds__(kBigThreads) void k_em_big(CompressArgs A)
 template <int D>
 struct CompF64 {
     double mu[D];
-    double L[ntri(D)];  // Cholesky factor, packed lower
+    double M[ntri(D)];  // inverse of the Cholesky factor, packed lower
     double lnw_c;       // ln w - D/2 ln(2 pi) - ln sqrt det
 };
 
-// not inlined: the normaliser pass and the component passes must evaluate
-// each term with the same instruction sequence
+// ln(w N(x; mu, Sigma)) = lnw_c - |M (x - mu)|^2 / 2.  Every product-sum is
+// an explicit fma and every other operation a single rounding, so each
+// inlined copy evaluates a term bit for bit alike: the normaliser pass and
+// the component passes see the same value.
 template <int D>
-__device__ __noinline__ double ln_term(const CompF64<D>& c, const double (&x)[D])
+__device__ __forceinline__ double ln_term(const CompF64<D>& c, const double (&x)[D])
 {
-    double y[D];
     if constexpr (D == 1) {
-        y[0] = (x[0] - c.mu[0]) / c.L[0];
-        return c.lnw_c - 0.5 * y[0] * y[0];
+        const double y0 = c.M[0] * (x[0] - c.mu[0]);
+        return fma(-0.5, y0 * y0, c.lnw_c);
     } else {
-        y[0] = (x[0] - c.mu[0]) / c.L[0];
-        y[1] = (x[1] - c.mu[1] - c.L[1] * y[0]) / c.L[3];
-        y[2] = (x[2] - c.mu[2] - c.L[2] * y[0] - c.L[4] * y[1]) / c.L[5];
-        return c.lnw_c - 0.5 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+        const double d0 = x[0] - c.mu[0], d1 = x[1] - c.mu[1], d2 = x[2] - c.mu[2];
+        const double y0 = c.M[0] * d0;
+        const double y1 = fma(c.M[1], d0, c.M[3] * d1);
+        const double y2 = fma(c.M[2], d0, fma(c.M[4], d1, c.M[5] * d2));
+        const double q = fma(y0, y0, fma(y1, y1, y2 * y2));
+        return fma(-0.5, q, c.lnw_c);
     }
 }
 
@@ -1565,8 +1568,7 @@ __device__ __forceinline__ bool make_f64(CompF64<D>& c, const double* mu, const 
     if (!chol<D, double>(Sd, L)) return false;
 #pragma unroll
     for (int i = 0; i < D; ++i) c.mu[i] = mu[i];
-#pragma unroll
-    for (int t = 0; t < ntri(D); ++t) c.L[t] = L[t];
+    tri_inv<D, double>(L, c.M);
     double lndet = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) lndet += log(L[tri_idx<D>(i, i)]);
@@ -1661,10 +1663,14 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
         for (int d = 0; d < D; ++d) xv[d] = vc[(size_t)i * D + d] - m[d];
     };
     // largest log term and the sum of exp(term - largest) over cf[0..K-1]
+    // (rolled loops: unrolled, the compiler would keep every component's
+    // parameters in registers across the particle loop)
     auto norm_at = [&](const double (&xv)[D], int K, double& mx, double& se) {
         mx = -INFINITY;
+#pragma unroll 1
         for (int j = 0; j < K; ++j) mx = fmax(mx, ln_term<D>(cf[j], xv));
         se = 0.0;
+#pragma unroll 1
         for (int j = 0; j < K; ++j) se += exp(ln_term<D>(cf[j], xv) - mx);
     };
     auto lse_at = [&](const double (&xv)[D], int K) {
@@ -1727,13 +1733,15 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
         }
         sync();
         // gamma_pk = a_p exp(l_k - mx_p) / sum_j exp(l_j - mx_p): a ratio of
-        // the same exponentials, so sum_k gamma_pk = a_p to rounding
+        // the same exponentials, so sum_k gamma_pk = a_p to rounding (the
+        // cache keeps 1 / sum)
         const bool cache = n <= CACHE;
         if (cache) {
             for (int i = tid; i < n; i += nthreads) {
-                double xv[D];
+                double xv[D], se;
                 load_x(i, xv);
-                norm_at(xv, K, mx_cache[i], sum_cache[i]);
+                norm_at(xv, K, mx_cache[i], se);
+                sum_cache[i] = 1.0 / se;
             }
         }
         sync();
@@ -1746,14 +1754,16 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
             for (int i = tid; i < n; i += nthreads) {
                 double xv[D];
                 load_x(i, xv);
-                double mx, se;
+                double mx, rse;
                 if (cache) {
                     mx = mx_cache[i];
-                    se = sum_cache[i];
+                    rse = sum_cache[i];
                 } else {
+                    double se;
                     norm_at(xv, K, mx, se);
+                    rse = 1.0 / se;
                 }
-                const double g = ac[i] * wscale * exp(ln_term<D>(ck, xv) - mx) / se;
+                const double g = ac[i] * wscale * exp(ln_term<D>(ck, xv) - mx) * rse;
                 double d[D];
 #pragma unroll
                 for (int q = 0; q < D; ++q) d[q] = xv[q] - ck.mu[q];
