@@ -180,6 +180,8 @@ def cpu_baseline(data, W, n_cells_sample, n_cells_single):
 
     oracle.build()
     threads = oracle.default_threads()
+    n_cells_sample = min(n_cells_sample, n_cells)
+    n_cells_single = min(n_cells_single, n_cells)
     n_all, t_all = run(n_cells_sample, threads)
     n_one, t_one = run(n_cells_single, 1)
     try:

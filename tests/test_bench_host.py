@@ -53,3 +53,17 @@ def test_conservation_check_finds_a_moment_error():
         rec.status = torch.tensor([0, 128, 0, 0], dtype=torch.int32)
         r = bench.conservation(rec, mom, counts, D, torch)
         assert r["cells_checked"] == 3 and r["lemons_skipped"] == 1 and r["max_rel_err"] < 1e-13
+
+
+def test_cpu_baseline_sample_is_clamped_to_the_batch():
+    """A batch with fewer cells than the sample sizes is sampled whole,
+    once per cell, and the line says so."""
+    import bench
+    rng = np.random.default_rng(3)
+    counts = np.array([40, 60, 50])
+    v = rng.normal(size=(counts.sum(), 3))
+    data = {"v": v, "alpha": np.ones(counts.sum()), "cell_off": np.concatenate([[0], np.cumsum(counts)])}
+    W = {"kmax": 4, "init_seed": 1, "D": 3, "dx": 1, "recon_seed": 2}
+    r = bench.cpu_baseline(data, W, 256, 16)
+    assert r["sample"].startswith("3 of 3 cells") and "%d particles" % counts.sum() in r["sample"]
+    assert r["single_thread"]["sample"].startswith("3 evenly spaced cells, %d particles" % counts.sum())
