@@ -231,6 +231,47 @@ def test_train_step_matches_oracle_gradients_and_adam():
     m.close()
 
 
+def test_adam_steps_match_torch_adam():
+    """Several training steps of the library (gm_warm_train_step: Adam on
+    FP32 master weights, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected)
+    against torch.optim.Adam, the library implementation of the published
+    method, fed the library's own gradient of each step: the moment
+    estimates, their bias corrections and the step count must carry over
+    from step to step.  FP64 reference, FP32 library: every parameter
+    within 2e-6 relative and 1e-4 of the learning rate."""
+    api = _api()
+    B = 128
+    d = _subset(synth.make("weibel_3v"), 256)
+    f, _, _ = _oracle_feature_bits(d)
+    rng = np.random.default_rng(17)
+    T = np.zeros((256, 160), np.float32)
+    for r in range(256):
+        k = rng.integers(1, 6)
+        w = np.sort(rng.dirichlet(np.ones(k)))[::-1]
+        for j in range(k):
+            T[r, 10 * j] = w[j]
+            T[r, 10 * j + 1:10 * j + 10] = rng.normal(size=9) * 0.5
+    Tg = torch.from_numpy(T).to(dev())
+    m = api.WarmStart(16, batch=B, seed=3)
+    lr = 2e-3
+    ref = torch.tensor(m.get_params().astype(np.float64), requires_grad=True)
+    opt = torch.optim.Adam([ref], lr=lr, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(6):
+        idx = torch.from_numpy(rng.permutation(256)[:B].astype(np.int32)).to(dev())
+        m.train_step(f, Tg, idx, lr=lr, lam=1.0)
+        g = m.gradients().astype(np.float64)
+        assert np.abs(g).max() > 0
+        opt.zero_grad()
+        ref.grad = torch.from_numpy(g)
+        opt.step()
+        got = m.get_params().astype(np.float64)
+        want = ref.detach().numpy()
+        err = np.abs(got - want)
+        print("step %d: max |library - torch Adam| %.2e (lr %.0e)" % (step + 1, err.max(), lr))
+        np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-4 * lr)
+    m.close()
+
+
 def test_decode_matches_oracle():
     api = _api()
     d = _edge_batch()

@@ -524,6 +524,69 @@ def test_outer_k_search_on_single_gaussian_cells(kmax):
     assert (outer["sweeps"] >= plain["sweeps"] + 2 * (plain["K"] - 1)).all()
 
 
+def test_outer_k_search_is_its_chain_of_single_runs():
+    """The outer search over K written out as its definition: the
+    converged single pass, then, from that state without its least probable
+    component (weights renormalised), a single pass started there, and so on
+    down to K = 1; the result is the run with the highest penalised L, with
+    the sweeps and component updates of all runs added.  Each link uses
+    the oracle's supplied-start path and its no-finish mode (both pinned
+    elsewhere); a wrong component removed, a missing renormalisation, a
+    comparison on the wrong L, a run dropped or a count not carried over
+    fails here.  The chain's supplied starts re-enter in the input
+    coordinates, so the runs agree to rounding: K, sweeps and updates
+    exactly, L to 1e-9."""
+    d = synth.make("weibel_3v")
+    off = d["cell_off"]
+    cells = [c for c in range(0, 200, 7) if 300 <= off[c + 1] - off[c] <= 900][:6]
+    assert len(cells) >= 4
+    idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in cells])
+    so = np.concatenate([[0], np.cumsum([off[c + 1] - off[c] for c in cells])]).astype(np.int64)
+    v, a = d["v"][idx], d["alpha"][idx]
+    kmax, seed, nc = 16, 11, len(cells)
+    outer = oracle.compress(v, a, so, kmax=kmax, seed=seed, mode=oracle.MODE_OUTER_K | oracle.MODE_NO_FINISH)
+    run = oracle.compress(v, a, so, kmax=kmax, seed=seed, mode=oracle.MODE_NO_FINISH)
+    best = {k: run[k].copy() for k in ("K", "omega", "mu", "sigma", "L_pen")}
+    sweeps = run["sweeps"].astype(np.int64)
+    visits = run["visits"].copy()
+    n_runs = np.ones(nc, np.int64)
+    while (run["K"] > 1).any():
+        live = run["K"] > 1
+        init = {"K": np.zeros(nc, np.int32), "omega": np.zeros((nc, kmax)), "mu": np.zeros((nc, kmax, 3)),
+                "sigma": np.zeros((nc, kmax, 6))}
+        for c in np.nonzero(live)[0]:
+            K = run["K"][c]
+            w = run["omega"][c, :K]
+            drop = int(np.argmin(w))  # smallest weight, lowest slot on ties
+            keep = [k for k in range(K) if k != drop]
+            init["K"][c] = K - 1
+            init["omega"][c, :K - 1] = w[keep] / w[keep].sum()
+            init["mu"][c, :K - 1] = run["mu"][c, keep]
+            init["sigma"][c, :K - 1] = run["sigma"][c, keep]
+        nxt = oracle.compress(v, a, so, kmax=kmax, seed=seed, mode=oracle.MODE_NO_FINISH, init=init)
+        assert not (nxt["status"][live] & oracle.STATUS["WARM_FALLBACK"]).any()
+        for c in np.nonzero(live)[0]:
+            sweeps[c] += nxt["sweeps"][c]
+            visits[c] += nxt["visits"][c]
+            n_runs[c] += 1
+            if nxt["L_pen"][c] > best["L_pen"][c]:
+                for k in best:
+                    best[k][c] = nxt[k][c]
+        run = {k: np.where(live.reshape((-1,) + (1,) * (nxt[k].ndim - 1)), nxt[k], run[k]) for k in run}
+        run["K"] = np.where(live, nxt["K"], 1)
+    print("runs per cell", n_runs.tolist(), "outer K", outer["K"].tolist(), "single-pass K",
+          oracle.compress(v, a, so, kmax=kmax, seed=seed)["K"].tolist())
+    assert (n_runs >= 2).all()
+    np.testing.assert_array_equal(outer["K"], best["K"])
+    np.testing.assert_array_equal(outer["sweeps"], sweeps)
+    np.testing.assert_array_equal(outer["visits"], visits)
+    np.testing.assert_allclose(outer["L_pen"], best["L_pen"], rtol=1e-9)
+    for c in range(nc):
+        K = best["K"][c]
+        np.testing.assert_allclose(outer["omega"][c, :K], best["omega"][c, :K], rtol=1e-7, atol=1e-10)
+        np.testing.assert_allclose(outer["mu"][c, :K], best["mu"][c, :K], rtol=1e-7, atol=1e-9)
+
+
 @pytest.mark.parametrize("name", ["weibel_3v", "mix_1v"])
 def test_likelihood_shifts_with_the_velocity_unit(name):
     """Scaling every velocity by s (a change of unit) maps the fit to the

@@ -145,3 +145,63 @@ def test_decode_without_frame_keeps_cold_start():
     dec = oracle.warm_decode(Y, fr, off, 16)
     assert (dec["K"] == 0).all()
     assert not dec["omega"].any() and not dec["mu"].any() and not dec["sigma"].any()
+
+
+def _tri_sym(s):
+    return np.array([[s[0], s[1], s[2]], [s[1], s[3], s[4]], [s[2], s[4], s[5]]])
+
+
+def test_decode_and_targets_follow_the_cell_frame():
+    """Decode and targets written out as maps between a cell's frame (mean
+    m, lower Cholesky factor L of its covariance) and the whitened network
+    space, checked for what those maps must satisfy whatever their formulas:
+    under a change of velocity coordinates v -> a + B v with B lower
+    triangular (so the new frame is a + B m, B L), decoding the same network
+    output gives means a + B mu and covariances B Sigma B^T with the same
+    K and weights, and the targets of a mixture moved the same way are
+    unchanged; adding a constant to every slot's logit changes nothing.  A
+    transposed frame factor, a mean added in the wrong space or a whitening
+    on the wrong side fails the first two."""
+    rng = np.random.default_rng(21)
+    d = synth.make("weibel_3v")
+    nc = 6
+    off = d["cell_off"][:nc + 1]
+    v, al = d["v"][:off[-1]], d["alpha"][:off[-1]]
+    _, fr = oracle.features(v, al, off)
+    Y = rng.normal(size=(nc, 160)) * 0.4
+    Y[:, 0::10] = rng.normal(size=(nc, 16)) * 2.0  # logits
+    a = rng.normal(size=3)
+    B = np.tril(rng.normal(size=(3, 3)) * 0.3) + np.diag(rng.uniform(0.5, 2.0, 3))
+    fr2 = fr.copy()
+    for c in range(nc):
+        L = np.array([[fr[c, 3], 0, 0], [fr[c, 4], fr[c, 5], 0], [fr[c, 6], fr[c, 7], fr[c, 8]]])
+        L2 = B @ L
+        fr2[c, :3] = a + B @ fr[c, :3]
+        fr2[c, 3:] = [L2[0, 0], L2[1, 0], L2[1, 1], L2[2, 0], L2[2, 1], L2[2, 2]]
+    d1 = oracle.warm_decode(Y, fr, off, 16)
+    d2 = oracle.warm_decode(Y, fr2, off, 16)
+    np.testing.assert_array_equal(d1["K"], d2["K"])
+    assert (d1["K"] >= 1).all()
+    np.testing.assert_allclose(d1["omega"], d2["omega"], rtol=1e-14)
+    iu = np.triu_indices(3)
+    for c in range(nc):
+        for q in range(d1["K"][c]):
+            np.testing.assert_allclose(d2["mu"][c, q], a + B @ d1["mu"][c, q], rtol=1e-12, atol=1e-12)
+            S2 = B @ _tri_sym(d1["sigma"][c, q]) @ B.T
+            np.testing.assert_allclose(d2["sigma"][c, q], S2[iu], rtol=1e-10, atol=1e-14)
+    # the same logits shifted by a constant decode alike
+    Ys = Y.copy()
+    Ys[:, 0::10] += 7.5
+    d3 = oracle.warm_decode(Ys, fr, off, 16)
+    for k in d1:
+        np.testing.assert_allclose(d3[k], d1[k], rtol=1e-12, atol=1e-15)
+    # targets of a mixture are invariant under the same move of mixture and frame
+    mix = oracle.compress(v, al, off, kmax=16, seed=3, max_sweeps=40)
+    mix2 = {"K": mix["K"], "omega": mix["omega"], "mu": mix["mu"].copy(), "sigma": mix["sigma"].copy()}
+    for c in range(nc):
+        for k in range(mix["K"][c]):
+            mix2["mu"][c, k] = a + B @ mix["mu"][c, k]
+            mix2["sigma"][c, k] = (B @ _tri_sym(mix["sigma"][c, k]) @ B.T)[iu]
+    t1 = oracle.warm_targets(mix, fr)
+    t2 = oracle.warm_targets(mix2, fr2)
+    np.testing.assert_allclose(t2, t1, rtol=1e-9, atol=1e-9)
