@@ -190,11 +190,17 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * matching number of 64-lane waves per workgroup, density terms kept in
  * registers or recomputed, and the standard build (up to 8 waves per
  * workgroup, up to 256 VGPRs per lane) or, for FP32 iterations, the lean
- * build (up to 16 waves, at most 128 VGPRs: twice the waves per SIMD).  gm_autotune measures, on the caller's batch,
+ * build (up to 16 waves, at most 128 VGPRs: twice the waves per SIMD).
+ * With FP32 iterations at kmax 16 the two buckets of cells above 2048
+ * particles always use their 16-wave lean build (4 and 8 particles per
+ * thread): a single long fit there can set the phase's length, and that
+ * build gives it the lowest per-update latency.  gm_autotune measures, on the caller's batch,
  * every non-empty bucket alone under each variant, keeps the fastest per
- * bucket, assigns the buckets to the four streams longest first onto the
- * least-loaded stream, times the concurrent EM phase of that plan against
- * the built-in plan, and installs the faster of the two for this device,
+ * bucket (and, as a second plan, the fastest lean build where there is
+ * one), gives each bucket a library stream of its own, longest first, times
+ * the concurrent EM phase of these plans and of the built-in plan (the
+ * median of three runs each, the plans in turn), and installs the fastest
+ * for this device,
  * D, kmax class (<= 8 or <= 16), precision and kind of start (warm when
  * init supplies mixtures).  Later gm_compress calls of that kind use it.
  * Arguments as for gm_compress (converged mode, no fixed sweeps); `out`

@@ -108,7 +108,21 @@ constexpr int kNumLaneOf(int b) { return b; }
 // persistent workgroups of the big-cell launch
 constexpr int kBigGrid = 64;
 
-EmPlan default_plan(int kt)
+// Buckets of cells above 2048 particles (kmax 16) hold few cells, and one
+// long fit among them can set the length of the whole EM phase: there the
+// per-update latency of a single cell matters more than the bucket's
+// throughput.  FP32 iterations run them with the 16-wave lean build (four
+// waves per SIMD, the cell's CU to itself).  On the Weibel-like batch one
+// 2049-particle cell running 1000 sweeps made the warm phase 9.6-10.4 ms
+// with it against 13.9-14.8 ms with the 8-wave builds, while a batch without
+// such a fit cannot tell the builds apart, so the tuner keeps this choice.
+constexpr int kChainMinN = 2048;
+inline bool chain_bucket(int kt, bool fp64, int b)
+{
+    return !fp64 && kt == 16 && gm::bucket_cfg(kt, b).max_n > kChainMinN;
+}
+
+EmPlan default_plan(int kt, bool fp64)
 {
     EmPlan p;
     for (int b = 0; b < gm::kNumBuckets; ++b) {
@@ -116,6 +130,12 @@ EmPlan default_plan(int kt)
         p.per_thread[b] = (int8_t)c.per_thread;
         p.mode[b] = (int8_t)(c.store_e ? gm::kModeStoreE : 0);
         p.waves[b] = (int8_t)c.waves;
+        if (chain_bucket(kt, fp64, b)) {
+            const int W = gm::em_max_waves(true);
+            p.per_thread[b] = (int8_t)(c.max_n / (64 * W));
+            p.mode[b] = (int8_t)gm::kModeLean;
+            p.waves[b] = (int8_t)W;
+        }
         p.lane[b] = (int8_t)(kNumLaneOf(b));
         p.order[b] = (int8_t)(gm::kNumBuckets - 1 - b);  // largest cells first
     }
@@ -131,7 +151,7 @@ EmPlan* plan_slot(int D, int kt, bool fp64, bool warm, bool create)
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
     EmPlan*& p = g_plans[dev][D == 3][kt == 16][fp64 ? 1 : 0][warm ? 1 : 0];
     if (!p && create) {
-        p = new EmPlan(default_plan(kt));
+        p = new EmPlan(default_plan(kt, fp64));
     }
     return p;
 }
@@ -265,7 +285,7 @@ int compress_run(const double* v, const double* alpha, const int64_t* cell_off, 
     // captured into a graph), in the order and lanes of the launch plan.
     {
         const EmPlan* tuned = plan_slot(D, kt, fp64, init && init->K, false);
-        const EmPlan p = tuned ? *tuned : default_plan(kt);
+        const EmPlan p = tuned ? *tuned : default_plan(kt, fp64);
         if (launch_em_phase(D, fp64, kt, p, a, n_cells, st)) return GM_EHIP;
     }
     prof_mark(EV_FIN, st);
@@ -523,6 +543,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
             if (var.lean && fp64) continue;
             const int waves = (max_n + 64 * var.per_thread - 1) / (64 * var.per_thread);
             if (waves < 1 || waves > gm::em_max_waves(var.lean)) continue;
+            if (chain_bucket(kt, fp64, b) && !(var.lean && waves == gm::em_max_waves(true))) continue;
             cand[b][ncand[b]][0] = vi;
             cand[b][ncand[b]][1] = waves;
             ++ncand[b];
@@ -538,7 +559,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     int best_c[gm::kNumBuckets];
     double lean_ms[gm::kNumBuckets];  // fastest lean-build candidate
     int lean_c[gm::kNumBuckets];
-    EmPlan trial = default_plan(kt);
+    EmPlan trial = default_plan(kt, fp64);
     for (int b = 0; b < gm::kNumBuckets; ++b) {
         best_ms[b] = lean_ms[b] = 0.0;
         best_c[b] = lean_c[b] = -1;
@@ -586,7 +607,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     // leave room on a CU for the other buckets' workgroups, which can beat
     // a variant that is faster alone.
     auto make_plan = [&](const int* choice, const double* ms) {
-        EmPlan t = default_plan(kt);
+        EmPlan t = default_plan(kt, fp64);
         int idx[gm::kNumBuckets];
         for (int b = 0; b < gm::kNumBuckets; ++b) {
             idx[b] = b;
@@ -621,18 +642,26 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     // keep whichever plan runs the concurrent phase fastest
     constexpr int kPlans = 3;
     double phase_ms[kPlans] = {0.0, 0.0, 0.0};
-    const EmPlan cands[kPlans] = {default_plan(kt), make_plan(best_c, best_ms), make_plan(pref_c, pref_ms)};
-    for (int pi = 0; pi < kPlans && rc == GM_OK; ++pi) {
-        double best = 1e30;
-        for (int rep = 0; rep < 2 && rc == GM_OK; ++rep) {
+    const EmPlan cands[kPlans] = {default_plan(kt, fp64), make_plan(best_c, best_ms), make_plan(pref_c, pref_ms)};
+    // each plan's phase time is the median of three runs, the plans run in
+    // turn (a drift of the device's clocks affects all of them alike): the
+    // concurrent phase varies from run to run with the order in which the
+    // buckets' workgroups reach the CUs, and a lucky minimum predicts the
+    // next batch worse than the median does
+    constexpr int kReps = 3;
+    double runs[kPlans][kReps] = {};
+    for (int rep = 0; rep < kReps && rc == GM_OK; ++rep)
+        for (int pi = 0; pi < kPlans && rc == GM_OK; ++pi) {
             float t = 0.f;
             if (requeue() || hipEventRecord(ev[0], st) != hipSuccess ||
                 launch_em_phase(D, fp64, kt, cands[pi], a, n_cells, st) || hipEventRecord(ev[1], st) != hipSuccess ||
                 hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess)
                 rc = GM_EHIP;
-            best = std::min(best, (double)t);
+            runs[pi][rep] = t;
         }
-        phase_ms[pi] = best;
+    for (int pi = 0; pi < kPlans; ++pi) {
+        std::sort(runs[pi], runs[pi] + kReps);
+        phase_ms[pi] = runs[pi][kReps / 2];
     }
     int pick = 0;
     for (int pi = 1; pi < kPlans; ++pi)
@@ -666,7 +695,7 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
 {
     if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || !variant) return GM_EINVAL;
     const int kt = kmax <= 8 ? 8 : 16;
-    EmPlan p = default_plan(kt);
+    EmPlan p = default_plan(kt, fp64 != 0);
     for (int b = 0; b < gm::kNumBuckets; ++b) {
         const int code = variant[b];
         const int P = code / 1000, W = (code / 10) % 100, mode = code % 10;
