@@ -80,6 +80,9 @@ def test_autotune_installs_a_working_plan():
         assert rep["builtin_em_ms"] > 0 and rep["tuned_em_ms"] > 0
         for code, lane in zip(rep["variant"], rep["lane"]):
             assert code // 1000 in (1, 2, 4, 8, 16) and code % 10 <= 3 and 0 <= lane <= 11
+        # FP32 at kmax 16: the buckets of cells above 2048 particles keep their
+        # 16-wave lean build (4 and 8 recomputed particles per thread)
+        assert rep["variant"][10] == 4162 and rep["variant"][11] == 8162, rep["variant"]
         tuned = host(comp.out.as_dict())
         again = host(comp(v, a, offg).as_dict())
         for k in ("K", "sweeps", "status"):
