@@ -186,7 +186,7 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * 4): run with GPU_MAX_HW_QUEUES >= 13 (set before the HIP runtime starts)
  * for them to overlap; with fewer, launches sharing a queue run one after
  * another (same results, longer EM phase).  A bucket can run with
- * several launch variants: particles per thread (1, 2, 4, 8, 16), the
+ * several launch variants: particles per thread (1, 2, 4, 5, 6, 7, 8, 16), the
  * matching number of 64-lane waves per workgroup, density terms kept in
  * registers or recomputed, and the standard build (up to 8 waves per
  * workgroup, up to 256 VGPRs per lane) or, for FP32 iterations, the lean
@@ -194,7 +194,9 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * With FP32 iterations at kmax 16 the two buckets of cells above 2048
  * particles always use their 16-wave lean build (4 and 8 particles per
  * thread): a single long fit there can set the phase's length, and that
- * build gives it the lowest per-update latency.  gm_autotune measures, on the caller's batch,
+ * build gives it the lowest per-update latency; the cells of 1025-1792
+ * particles run by default as four waves of 5, 6 or 7 register-resident
+ * particles per thread (one wave per SIMD).  gm_autotune measures, on the caller's batch,
  * every non-empty bucket alone under each variant, keeps the fastest per
  * bucket (and, as a second plan, the fastest lean build where there is
  * one), gives each bucket a library stream of its own, longest first, times
@@ -223,8 +225,9 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
  * (nullable) lane[b] for the twelve buckets, coded as in the report; a
  * variant must be built (see above) and cover the bucket: 64 * per_thread *
  * waves >= the bucket's largest cell, waves <= 8 (16 for lean builds).
- * Built: standard 1, 2, 4 register-resident (8 at kmax <= 8) and 8, 16
- * recomputed; lean (FP32 only) 1, 2 register-resident and 4, 8 recomputed.
+ * Built: standard 1, 2, 4 register-resident (8 at kmax <= 8; 5, 6, 7 for
+ * D = 3, FP32, kmax > 8) and 8, 16 recomputed; lean (FP32 only) 1, 2
+ * register-resident and 4, 8 recomputed.
  * GM_EINVAL otherwise. */
 int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant,
                     const int32_t* lane);

@@ -56,7 +56,11 @@ constexpr int kMaxCellParticles = 8192;
 // only.  A variant fits a bucket when 64 * waves * per_thread >= max_n with
 // waves = ceil(max_n / (64 * per_thread)) <= the build's waves.
 // Register-resident densities with 8 particles per thread are built for
-// kmax 8 only (16 slots x 8 particles do not fit the register file).
+// kmax 8 only (16 slots x 8 particles do not fit the register file); with
+// 5, 6 and 7 for 3V FP32 iterations at kmax 16 only, so that the cells of
+// 1025-1792 particles run as four waves, one per SIMD: with five to seven
+// waves some SIMD carries two of the cell's waves and every component
+// update waits for it.
 // Launch mode bits: kModeStoreE (densities in registers), kModeLean.
 constexpr int kModeStoreE = 1;
 constexpr int kModeLean = 2;
@@ -65,11 +69,18 @@ struct EmVariant {
     bool store_e;
     bool lean;
 };
-constexpr int kNumVariants = 10;
+constexpr int kNumVariants = 13;
 constexpr EmVariant kVariants[kNumVariants] = {{1, true, false}, {2, true, false}, {4, true, false},
                                               {8, true, false}, {8, false, false}, {16, false, false},
                                               {1, true, true},  {2, true, true},  {4, false, true},
-                                              {8, false, true}};
+                                              {8, false, true}, {5, true, false}, {6, true, false},
+                                              {7, true, false}};
+// the 5-, 6- and 7-particle register-resident builds exist for D = 3, FP32,
+// kmax 16 only
+__host__ __device__ constexpr bool em_variant_built(int D, int kt, bool fp64, int per_thread, bool store_e)
+{
+    return !(store_e && per_thread >= 5 && per_thread <= 7) || (D == 3 && kt == 16 && !fp64);
+}
 constexpr int kEmMaxThreads = 512;
 constexpr int kEmLeanThreads = 1024;
 __host__ __device__ constexpr int em_max_waves(bool lean) { return (lean ? kEmLeanThreads : kEmMaxThreads) / 64; }
