@@ -226,7 +226,7 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
  * variant must be built (see above) and cover the bucket: 64 * per_thread *
  * waves >= the bucket's largest cell, waves <= 8 (16 for lean builds).
  * Built: standard 1, 2, 4 register-resident (8 at kmax <= 8; 5, 6, 7 for
- * D = 3, FP32, kmax > 8) and 8, 16 recomputed; lean (FP32 only) 1, 2
+ * FP32 at kmax > 8) and 8, 16 recomputed; lean (FP32 only) 1, 2
  * register-resident and 4, 8 recomputed.
  * GM_EINVAL otherwise. */
 int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant,

@@ -122,7 +122,7 @@ inline bool chain_bucket(int kt, bool fp64, int b)
     return !fp64 && kt == 16 && gm::bucket_cfg(kt, b).max_n > kChainMinN;
 }
 
-// The cells of 1025-1792 particles (3V, FP32, kmax 16) run as four waves,
+// The cells of 1025-1792 particles (FP32, kmax 16) run as four waves,
 // one per SIMD, with 5, 6 or 7 register-resident particles per thread
 // instead of five to seven waves of 4: every update then waits for a SIMD
 // with one of the cell's waves, not two.  On the Weibel-like batch the warm
@@ -130,7 +130,7 @@ inline bool chain_bucket(int kt, bool fp64, int b)
 inline bool four_wave_bucket(int D, int kt, bool fp64, int b)
 {
     const int n = gm::bucket_cfg(kt, b).max_n;
-    return D == 3 && kt == 16 && !fp64 && n > 1024 && n <= 1792;
+    return (void)D, kt == 16 && !fp64 && n > 1024 && n <= 1792;
 }
 
 EmPlan default_plan(int D, int kt, bool fp64)

@@ -1875,7 +1875,7 @@ inline bool with_variant_kernel(int per_thread, int mode, F&& f)
         case 5:
         case 6:
         case 7:
-            if constexpr (KMAX == 16 && D == 3 && std::is_same<R, float>::value) {
+            if constexpr (KMAX == 16 && std::is_same<R, float>::value) {
                 if (per_thread == 5) f(k_em<D, KMAX, 5, true, R, false>);
                 else if (per_thread == 6) f(k_em<D, KMAX, 6, true, R, false>);
                 else f(k_em<D, KMAX, 7, true, R, false>);

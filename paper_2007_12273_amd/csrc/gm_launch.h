@@ -57,7 +57,7 @@ constexpr int kMaxCellParticles = 8192;
 // waves = ceil(max_n / (64 * per_thread)) <= the build's waves.
 // Register-resident densities with 8 particles per thread are built for
 // kmax 8 only (16 slots x 8 particles do not fit the register file); with
-// 5, 6 and 7 for 3V FP32 iterations at kmax 16 only, so that the cells of
+// 5, 6 and 7 for FP32 iterations at kmax 16 only, so that the cells of
 // 1025-1792 particles run as four waves, one per SIMD: with five to seven
 // waves some SIMD carries two of the cell's waves and every component
 // update waits for it.
@@ -75,11 +75,11 @@ constexpr EmVariant kVariants[kNumVariants] = {{1, true, false}, {2, true, false
                                               {1, true, true},  {2, true, true},  {4, false, true},
                                               {8, false, true}, {5, true, false}, {6, true, false},
                                               {7, true, false}};
-// the 5-, 6- and 7-particle register-resident builds exist for D = 3, FP32,
+// the 5-, 6- and 7-particle register-resident builds exist for FP32 at
 // kmax 16 only
 __host__ __device__ constexpr bool em_variant_built(int D, int kt, bool fp64, int per_thread, bool store_e)
 {
-    return !(store_e && per_thread >= 5 && per_thread <= 7) || (D == 3 && kt == 16 && !fp64);
+    return (void)D, !(store_e && per_thread >= 5 && per_thread <= 7) || (kt == 16 && !fp64);
 }
 constexpr int kEmMaxThreads = 512;
 constexpr int kEmLeanThreads = 1024;

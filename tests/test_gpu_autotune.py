@@ -25,7 +25,7 @@ def _codes(kmax, variant, D=3):
     P, se, lean = variant
     if se and P == 8 and kmax > 8:
         return None
-    if se and 5 <= P <= 7 and (kmax <= 8 or D != 3):
+    if se and 5 <= P <= 7 and kmax <= 8:
         return None
     out = []
     for m in (MAXN8 if kmax <= 8 else MAXN16):
