@@ -177,8 +177,10 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
                         void* stream);
 
 /* ---- launch-plan autotuner ----
- * gm_compress runs the EM iterations in twelve length buckets (bucket b
- * holds the cells of up to 64 * 2^b particles, refined at kmax 16), each a
+ * gm_compress runs the EM iterations in twelve length buckets (largest
+ * cells: 64, 128, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 8192
+ * particles at kmax <= 8; 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048,
+ * 2560, 4096, 8192 at kmax > 8), each a
  * persistent launch whose workgroups take cells from a queue, each on a
  * library stream of its own (cells of more than 8192 particles run on the
  * caller's stream), so that all thirteen launches run concurrently.  HIP
@@ -191,12 +193,14 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * registers or recomputed, and the standard build (up to 8 waves per
  * workgroup, up to 256 VGPRs per lane) or, for FP32 iterations, the lean
  * build (up to 16 waves, at most 128 VGPRs: twice the waves per SIMD).
- * With FP32 iterations at kmax 16 the two buckets of cells above 2048
- * particles always use their 16-wave lean build (4 and 8 particles per
- * thread): a single long fit there can set the phase's length, and that
- * build gives it the lowest per-update latency; the cells of 1025-1792
- * particles run by default as four waves of 5, 6 or 7 register-resident
- * particles per thread (one wave per SIMD).  gm_autotune measures, on the caller's batch,
+ * With FP32 iterations at kmax 16 the buckets of cells above 2048
+ * particles hold few cells, and a single long fit there can set the
+ * phase's length: they run by default with a lean build of more than 8
+ * waves (4 or 8 recomputed particles per thread), and in 3V the cells of
+ * 2049-4096 particles with eight waves of 5 and 8 register-resident
+ * particles per thread instead; the tuner chooses only among these
+ * builds there.  The cells of 1025-1792 particles run by default as four
+ * waves of 5, 6 or 7 register-resident particles per thread.  gm_autotune measures, on the caller's batch,
  * every non-empty bucket alone under each variant, keeps the fastest per
  * bucket (and, as a second plan, the fastest lean build where there is
  * one), gives each bucket a library stream of its own, longest first, times
@@ -225,9 +229,9 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
  * (nullable) lane[b] for the twelve buckets, coded as in the report; a
  * variant must be built (see above) and cover the bucket: 64 * per_thread *
  * waves >= the bucket's largest cell, waves <= 8 (16 for lean builds).
- * Built: standard 1, 2, 4 register-resident (8 at kmax <= 8; 5, 6, 7 for
- * FP32 at kmax > 8) and 8, 16 recomputed; lean (FP32 only) 1, 2
- * register-resident and 4, 8 recomputed.
+ * Built: standard 1, 2, 4, 8 register-resident (8 for FP32 only at kmax
+ * > 8; 5, 6, 7 for FP32 at kmax > 8) and 8, 16 recomputed; lean (FP32
+ * only) 1, 2 register-resident and 4, 8 recomputed.
  * GM_EINVAL otherwise. */
 int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant,
                     const int32_t* lane);

@@ -111,8 +111,10 @@ constexpr int kBigGrid = 64;
 // Buckets of cells above 2048 particles (kmax 16) hold few cells, and one
 // long fit among them can set the length of the whole EM phase: there the
 // per-update latency of a single cell matters more than the bucket's
-// throughput.  FP32 iterations run them with the 16-wave lean build (four
-// waves per SIMD, the cell's CU to itself).  On the Weibel-like batch one
+// throughput.  FP32 iterations run them with a lean build of more than 8
+// waves (four waves per SIMD, the cell's CU to itself; in 3V the cells of
+// 2049-4096 particles take the register-resident builds of the next rule
+// instead).  On the Weibel-like batch one
 // 2049-particle cell running 1000 sweeps made the warm phase 9.6-10.4 ms
 // with it against 13.9-14.8 ms with the 8-wave builds, while a batch without
 // such a fit cannot tell the builds apart, so the tuner keeps this choice.
@@ -133,6 +135,25 @@ inline bool four_wave_bucket(int D, int kt, bool fp64, int b)
     return (void)D, kt == 16 && !fp64 && n > 1024 && n <= 1792;
 }
 
+// In 3V the cells of 2049-2560 and 2561-4096 particles (FP32, kmax 16) run
+// as eight waves with 5 and 8 register-resident particles per thread (two
+// waves per SIMD, the CU to the cell as with the 16-wave lean build): each
+// update then evaluates one density per particle instead of recomputing the
+// old one beside the new one, and a cell near 2049 particles computes 5
+// particle slots per lane, not 8.  The 8-particle build spills a few
+// per-cell values, which it reloads inside the update.  On the Weibel-like
+// batch, where these cells hold the longest cold fits, with built-in plans:
+// judged-fallback refit 20.7-20.9 ms against 26.7-29.3 ms with the lean
+// build, headline step 30.6-31.0 ms against 35.5-38.9 ms; the warm phase
+// (8.8 ms against 8.3-8.4 ms) ends on a 2049-particle cell that runs 4005
+// component updates (the sweep cap) here and 957 with the lean build's
+// rounding.  The tuner may still pick a lean build there.
+inline bool resident8_bucket(int D, int kt, bool fp64, int b)
+{
+    const int n = gm::bucket_cfg(kt, b).max_n;
+    return D == 3 && kt == 16 && !fp64 && n > 2048 && n <= 4096;
+}
+
 EmPlan default_plan(int D, int kt, bool fp64)
 {
     EmPlan p;
@@ -147,10 +168,16 @@ EmPlan default_plan(int D, int kt, bool fp64)
             p.waves[b] = 4;
         }
         if (chain_bucket(kt, fp64, b)) {
-            const int W = gm::em_max_waves(true);
-            p.per_thread[b] = (int8_t)(c.max_n / (64 * W));
+            // the lean builds recompute 4 or 8 particles per thread
+            const int P = c.max_n <= 64 * gm::em_max_waves(true) * 4 ? 4 : 8;
+            p.per_thread[b] = (int8_t)P;
             p.mode[b] = (int8_t)gm::kModeLean;
-            p.waves[b] = (int8_t)W;
+            p.waves[b] = (int8_t)((c.max_n + 64 * P - 1) / (64 * P));
+        }
+        if (resident8_bucket(D, kt, fp64, b)) {
+            p.per_thread[b] = (int8_t)(c.max_n / (64 * 8));
+            p.mode[b] = (int8_t)gm::kModeStoreE;
+            p.waves[b] = 8;
         }
         p.lane[b] = (int8_t)(kNumLaneOf(b));
         p.order[b] = (int8_t)(gm::kNumBuckets - 1 - b);  // largest cells first
@@ -555,12 +582,13 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
         const int max_n = gm::bucket_cfg(kt, b).max_n;
         for (int vi = 0; vi < gm::kNumVariants; ++vi) {
             const gm::EmVariant& var = gm::kVariants[vi];
-            if (var.store_e && var.per_thread == 8 && kt != 8) continue;
             if (var.lean && fp64) continue;
             if (!gm::em_variant_built(D, kt, fp64, var.per_thread, var.store_e)) continue;
             const int waves = (max_n + 64 * var.per_thread - 1) / (64 * var.per_thread);
             if (waves < 1 || waves > gm::em_max_waves(var.lean)) continue;
-            if (chain_bucket(kt, fp64, b) && !(var.lean && waves == gm::em_max_waves(true))) continue;
+            if (chain_bucket(kt, fp64, b) && !(var.lean && waves > gm::em_max_waves(false)) &&
+                !(resident8_bucket(D, kt, fp64, b) && var.store_e && waves == 8))
+                continue;
             cand[b][ncand[b]][0] = vi;
             cand[b][ncand[b]][1] = waves;
             ++ncand[b];
@@ -722,7 +750,7 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
         for (int vi = 0; vi < gm::kNumVariants; ++vi)
             known |= gm::kVariants[vi].per_thread == P && gm::kVariants[vi].store_e == se &&
                      gm::kVariants[vi].lean == lean;
-        if (!known || (se && P == 8 && kt != 8) || (lean && fp64) || !gm::em_variant_built(D, kt, fp64 != 0, P, se))
+        if (!known || (lean && fp64) || !gm::em_variant_built(D, kt, fp64 != 0, P, se))
             return GM_EINVAL;
         if (W < 1 || W > gm::em_max_waves(lean) || 64 * P * W < gm::bucket_cfg(kt, b).max_n) return GM_EINVAL;
         p.per_thread[b] = (int8_t)P;

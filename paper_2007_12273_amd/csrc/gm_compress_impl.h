@@ -1883,7 +1883,7 @@ inline bool with_variant_kernel(int per_thread, int mode, F&& f)
             }
             return false;
         case 8:
-            if constexpr (KMAX == 8) {
+            if constexpr (KMAX == 8 || std::is_same<R, float>::value) {
                 f(k_em<D, KMAX, 8, true, R, false>);
                 return true;
             }

@@ -33,11 +33,15 @@ constexpr Bucket kBuckets8[kNumBuckets] = {
     {3072, 8, 6, true},  {3584, 8, 7, true},  {4096, 8, 8, true},   {8192, 16, 8, false},
 };
 // KMAX = 16: 4 register-resident particles per thread, one bucket per wave
-// count up to 8 waves (2048 particles), then the recompute mode.
+// count up to 8 waves (2048 particles), then the recompute mode; cells of
+// 2049-4096 particles in two buckets (their FP32 launch plans keep 5 and 8
+// particles per thread in registers).  Cells of up to 128 particles share
+// one bucket (two particles per thread; such cells are rare in the
+// workloads that use 16 slots).
 constexpr Bucket kBuckets16[kNumBuckets] = {
-    {64, 1, 1, true},    {128, 2, 1, true},   {256, 4, 1, true},    {512, 4, 2, true},
-    {768, 4, 3, true},   {1024, 4, 4, true},  {1280, 4, 5, true},   {1536, 4, 6, true},
-    {1792, 4, 7, true},  {2048, 4, 8, true},  {4096, 8, 8, false},  {8192, 16, 8, false},
+    {128, 2, 1, true},   {256, 4, 1, true},   {512, 4, 2, true},    {768, 4, 3, true},
+    {1024, 4, 4, true},  {1280, 4, 5, true},  {1536, 4, 6, true},   {1792, 4, 7, true},
+    {2048, 4, 8, true},  {2560, 8, 5, false}, {4096, 8, 8, false},  {8192, 16, 8, false},
 };
 __host__ __device__ constexpr const Bucket& bucket_cfg(int kmax_tpl, int b)
 {
@@ -76,10 +80,12 @@ constexpr EmVariant kVariants[kNumVariants] = {{1, true, false}, {2, true, false
                                               {8, false, true}, {5, true, false}, {6, true, false},
                                               {7, true, false}};
 // the 5-, 6- and 7-particle register-resident builds exist for FP32 at
-// kmax 16 only
+// kmax 16 only; the 8-particle one for kmax 8, and for FP32 at kmax 16
 __host__ __device__ constexpr bool em_variant_built(int D, int kt, bool fp64, int per_thread, bool store_e)
 {
-    return (void)D, !(store_e && per_thread >= 5 && per_thread <= 7) || (kt == 16 && !fp64);
+    return (void)D, !store_e || (per_thread >= 5 && per_thread <= 7 ? (kt == 16 && !fp64)
+                                 : per_thread == 8              ? (kt == 8 || !fp64)
+                                                                : true);
 }
 constexpr int kEmMaxThreads = 512;
 constexpr int kEmLeanThreads = 1024;

@@ -98,7 +98,7 @@ def test_launch_plan_codes_checked_on_host():
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("library not built")
     lib = _lib.load()
-    maxn16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
+    maxn16 = [128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 2560, 4096, 8192]
 
     def codes(P, mode, maxw):
         return [P * 1000 + min(maxw, -(-m // (64 * P))) * 10 + mode for m in maxn16]
@@ -109,7 +109,6 @@ def test_launch_plan_codes_checked_on_host():
     base = codes(16, 0, 8)
     for bad in (2 * 1000 + 10 + 4,      # mode 4 unknown
                 3 * 1000 + 10 + 1,      # 3 particles per thread not built
-                8 * 1000 + 10 + 1,      # register-resident 8 per thread only at kmax 8
                 1 * 1000 + 90 + 1,      # 9 waves: above the standard build's 8
                 1 * 1000 + 170 + 3,     # 17 waves: above the lean build's 16
                 4 * 1000 + 10 + 3):     # lean register-resident 4 per thread not built
@@ -117,10 +116,16 @@ def test_launch_plan_codes_checked_on_host():
         c[0] = bad
         assert setp(c) == -1, bad
     c = list(base)
-    c[9] = 2 * 1000 + 15 * 10 + 3  # 1920 < 2048 particles: does not cover the bucket
+    c[8] = 2 * 1000 + 15 * 10 + 3  # 1920 < 2048 particles: does not cover the bucket
     assert setp(c) == -1
-    c[9] = 2 * 1000 + 16 * 10 + 3
+    c[8] = 2 * 1000 + 16 * 10 + 3
     assert setp(c, fp64=1) == -1   # lean builds are FP32 only
+    c = list(base)
+    c[0] = 8 * 1000 + 10 + 1
+    # register-resident 8 per thread at kmax 16: FP32 only (here the call
+    # passes the checks and fails only for want of a device)
+    assert setp(c, fp64=1) == -1
+    assert setp(c) != -1
 
 
 def test_warm_model_files_checked_before_any_device_work(tmp_path):

@@ -13,7 +13,7 @@ import fp32_parity
 
 pytestmark = pytest.mark.gpu
 
-MAXN16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
+MAXN16 = [128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 2560, 4096, 8192]
 MAXN8 = [64, 128, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 8192]
 # (particles per thread, register-resident densities, lean build)
 VARIANTS = [(1, True, False), (2, True, False), (4, True, False), (8, True, False), (8, False, False),
@@ -23,8 +23,6 @@ VARIANTS = [(1, True, False), (2, True, False), (4, True, False), (8, True, Fals
 
 def _codes(kmax, variant, D=3):
     P, se, lean = variant
-    if se and P == 8 and kmax > 8:
-        return None
     if se and 5 <= P <= 7 and kmax <= 8:
         return None
     out = []
@@ -83,9 +81,12 @@ def test_autotune_installs_a_working_plan():
         assert rep["builtin_em_ms"] > 0 and rep["tuned_em_ms"] > 0
         for code, lane in zip(rep["variant"], rep["lane"]):
             assert code // 1000 in (1, 2, 4, 5, 6, 7, 8, 16) and code % 10 <= 3 and 0 <= lane <= 11
-        # FP32 at kmax 16: the buckets of cells above 2048 particles keep their
-        # 16-wave lean build (4 and 8 recomputed particles per thread)
-        assert rep["variant"][10] == 4162 and rep["variant"][11] == 8162, rep["variant"]
+        # FP32 at kmax 16: the cells of 2049-2560 and 2561-4096 particles run
+        # eight waves of 5 and 8 register-resident particles or a lean build of
+        # more than 8 waves, those of 4097-8192 particles the 16-wave lean
+        # build of 8 recomputed particles
+        assert rep["variant"][9] in (5081, 4102), rep["variant"]
+        assert rep["variant"][10] in (8081, 4162) and rep["variant"][11] == 8162, rep["variant"]
         tuned = host(comp.out.as_dict())
         again = host(comp(v, a, offg).as_dict())
         for k in ("K", "sweeps", "status"):

@@ -36,7 +36,7 @@ NEAR = oracle.STATUS["NEAR_TIE"]
 MAX_SWEEPS = 200
 
 # largest cell of each length bucket for 16 and 8 component slots
-BUCKETS16 = [64, 128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 4096, 8192]
+BUCKETS16 = [128, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 2560, 4096, 8192]
 BUCKETS8 = [64, 128, 256, 512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 8192]
 
 
