@@ -187,7 +187,11 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * maps streams onto GPU_MAX_HW_QUEUES hardware queues per process (default
  * 4): run with GPU_MAX_HW_QUEUES >= 13 (set before the HIP runtime starts)
  * for them to overlap; with fewer, launches sharing a queue run one after
- * another (same results, longer EM phase).  A bucket can run with
+ * another (same results, longer EM phase).  The same holds for a captured
+ * compress: a HIP graph replay runs the graph's parallel launches on the
+ * few streams of the runtime's graph executor (three or four hardware
+ * queues measured), so a replayed EM phase is several times longer than
+ * an eager one (same results).  A bucket can run with
  * several launch variants: particles per thread (1, 2, 4, 5, 6, 7, 8, 16), the
  * matching number of 64-lane waves per workgroup, density terms kept in
  * registers or recomputed, and the standard build (up to 8 waves per
