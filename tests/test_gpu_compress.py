@@ -153,12 +153,14 @@ def test_fp32_converged_mode():
 
 def test_edge_cells_and_all_buckets():
     """Empty, tiny, n <= n_min, non-finite, singular and every length bucket
-    (64 .. 8192 particles, both register-resident and recompute modes), and
-    both sides of the finish's split at 512 particles (one wave per cell up
-    to it, a workgroup above)."""
+    (64 .. 8192 particles, both register-resident and recompute modes, both
+    sides of the bucket limits 128, 2048, 2560 and 4096), and both sides of
+    the finish's split at 512 particles (one wave per cell up to it, a
+    workgroup above)."""
     rng = np.random.default_rng(5)
     D = 3
-    sizes = [0, 1, 5, 10, 11, 40, 64, 65, 128, 200, 256, 300, 512, 513, 700, 1024, 1500, 2048, 2500, 4096, 5000, 8192]
+    sizes = [0, 1, 5, 10, 11, 40, 64, 65, 128, 129, 200, 256, 300, 512, 513, 700, 1024, 1500, 2048, 2049, 2500, 2560,
+             2561, 4096, 4097, 5000, 8192]
     parts = [synth.random_cells(100 + i, 1, D, n, n, k_lo=2, k_hi=3) if n > 0 else None for i, n in enumerate(sizes)]
     vs, al = [], []
     for n, p in zip(sizes, parts):
