@@ -26,6 +26,9 @@ The perceptron is trained first (outside the timed region) on plain-EM fits
 of 16 fresh batches of cells of the same recipe (data seeds 5000-5015).  EM
 launch plans are tuned (gm_autotune) on a held-out batch of the same recipe
 (data seed 5099), not on the measured batch; the refit uses the cold plan.
+With --plan-cache the plans come from a launch-plan file written by an
+earlier run on the same kind of device (gm_autotune_load), or are tuned and
+saved to it.
 
 Prints one JSON line with the roofline of the dominant kernel (the EM
 sweeps, bound by FP32 vector ALU) from HIP events recorded around those
@@ -118,6 +121,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     p.add_argument("--no-tune", action="store_true", help="keep the built-in EM launch plans (no gm_autotune)")
+    p.add_argument("--plan-cache", default=None,
+                   help="launch-plan file: load the plans tuned earlier on this kind of device from it instead of "
+                        "tuning (when it holds any), else tune on the held-out batch and save them to it")
     p.add_argument("--no-pool", action="store_true",
                    help="generate the training cells in this process (no child processes; for profiler runs)")
     p.add_argument("--visits-out", default=None,
@@ -448,7 +454,12 @@ def main():
         recon(r.K, r.omega, r.mu, r.sigma, r.moments, W["recon_seed"])
 
     tune = {}
-    if not args.no_tune:
+    cached = 0
+    if not args.no_tune and args.plan_cache and os.path.exists(args.plan_cache):
+        cached = api.autotune_load(args.plan_cache)
+        log("launch plans loaded from %s: %d" % (args.plan_cache, cached))
+        tune["plan_cache"] = {"path": args.plan_cache, "plans_loaded": cached}
+    if not args.no_tune and not cached:
         # EM launch plans tuned on a held-out batch of the same recipe
         # (outside the timed region), separately for the cold and the warm
         # start; the measured batch is never tuned on
@@ -461,7 +472,9 @@ def main():
         torch.cuda.synchronize()
         del hd, hv, ha, ho, hc
         log("autotune on the held-out batch: %s" % {k: (round(r["builtin_em_ms"], 2), round(r["tuned_em_ms"], 2))
-                                                    for k, r in tune.items()})
+                                                    for k, r in tune.items() if k in ("plain_em", "warm")})
+        if args.plan_cache:
+            api.autotune_save(args.plan_cache)
     ms_cold = time_steps(cold_step, args.steps, args.warmup, torch)
     log("cold: %.3f ms/step" % ms_cold)
     graph = {}
@@ -625,8 +638,9 @@ def main():
     if graph:
         line["hip_graph_replay"] = graph
     if tune:
-        line["autotune"] = {k: {"builtin_em_ms": r["builtin_em_ms"], "tuned_em_ms": r["tuned_em_ms"],
-                                "variant": r["variant"], "lane": r["lane"]} for k, r in tune.items()}
+        line["autotune"] = {k: ({"builtin_em_ms": r["builtin_em_ms"], "tuned_em_ms": r["tuned_em_ms"],
+                                 "variant": r["variant"], "lane": r["lane"]} if k != "plan_cache" else r)
+                            for k, r in tune.items()}
     if args.copy_check:
         src = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

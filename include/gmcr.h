@@ -243,6 +243,33 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
 /* Forget every tuned plan; gm_compress returns to the built-in plans. */
 int gm_autotune_reset(void);
 
+/* The plan gm_compress uses on the current device for (D, kmax class,
+ * fp64, warm): variant[b] coded as in the report, and (nullable) lane[b]
+ * and order[b] (launch order, 0 first) for the twelve buckets, caller-owned
+ * arrays of 12.  Returns 1 for a tuned, hand-set or loaded plan, 0 for the
+ * built-in one (also when no device is visible), GM_EINVAL for bad
+ * arguments. */
+int gm_autotune_get(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, int32_t* variant, int32_t* lane,
+                    int32_t* order);
+
+/* Launch-plan cache file (plain text, one plan per line:
+ *   gmcr-plan 1 <arch> <CUs> <D> <kmax class 8|16> <fp64> <warm>
+ *   variant[12] lane[12] order[12]),
+ * keyed by the device (architecture name and CU count), D, kmax class,
+ * precision and kind of start, with the variant, stream and launch order of
+ * every length bucket.  gm_autotune_save writes the current device's tuned
+ * plans to `path`, keeping the lines of other devices already in the file;
+ * GM_EINVAL (NULL or empty path), GM_EHIP (no device), GM_EIO.
+ * gm_autotune_load reads `path` and installs the plans whose device key is
+ * the current device's, each checked as by gm_autotune_set (and the order a
+ * permutation of the buckets); blank lines and lines starting with '#' are
+ * skipped.  A malformed or invalid line rejects the whole file before any
+ * plan is installed (GM_EINVAL); GM_EIO if the file cannot be read.
+ * Returns the number of plans installed.  Not safe against concurrent
+ * gm_compress or gm_autotune calls. */
+int gm_autotune_save(const char* path);
+int gm_autotune_load(const char* path);
+
 /* ---- standard EM with K-means start and Anderson acceleration ----
  * The non-adaptive EM of Sec. 3.4 (fixed K, joint E-step, weights N_k / N),
  * as the paper uses to study faster convergence.  Per cell, K0 = min(K, n)

@@ -43,6 +43,7 @@ class GmInit(ctypes.Structure):
 
 EXPORTS = ("gm_opts_default", "gm_compress_workspace", "gm_compress", "gm_compress_noalloc", "gm_compress_warm",
            "gm_compress_warm_workspace", "gm_warm_model_kmax", "gm_warm_infer", "gm_autotune", "gm_autotune_set", "gm_autotune_reset",
+           "gm_autotune_get", "gm_autotune_save", "gm_autotune_load",
            "gm_reconstruct_workspace", "gm_reconstruct_tensor", "gm_project", "gm_gauss_workspace", "gm_deposit",
            "gm_gauss_correct", "gm_compress_standard_workspace", "gm_compress_standard",
            "gm_reconstruct", "gm_warm_param_count", "gm_warm_create", "gm_warm_destroy", "gm_warm_get_params",
@@ -92,6 +93,12 @@ def load():
     L.gm_autotune_set.restype = ctypes.c_int
     L.gm_autotune_reset.argtypes = []
     L.gm_autotune_reset.restype = ctypes.c_int
+    L.gm_autotune_get.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    L.gm_autotune_get.restype = ctypes.c_int
+    L.gm_autotune_save.argtypes = [ctypes.c_char_p]
+    L.gm_autotune_save.restype = ctypes.c_int
+    L.gm_autotune_load.argtypes = [ctypes.c_char_p]
+    L.gm_autotune_load.restype = ctypes.c_int
     L.gm_reconstruct_workspace.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.gm_reconstruct_workspace.restype = ctypes.c_size_t
     L.gm_reconstruct.argtypes = [P, P, P, P, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,

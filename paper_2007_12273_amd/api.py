@@ -367,6 +367,30 @@ def autotune_reset():
     check(_lib.load().gm_autotune_reset(), "gm_autotune_reset")
 
 
+def autotune_get(D, kmax, fp64=False, warm=False):
+    """The EM launch plan gm_compress uses for (D, kmax class, fp64, warm) on
+    the current device: dict of variant codes, lanes and launch order per
+    bucket, and whether it is a tuned (or hand-set, or loaded) plan."""
+    va, la, oa = (ctypes.c_int32 * 12)(), (ctypes.c_int32 * 12)(), (ctypes.c_int32 * 12)()
+    rc = _lib.load().gm_autotune_get(D, kmax, 1 if fp64 else 0, 1 if warm else 0, va, la, oa)
+    check(min(rc, 0), "gm_autotune_get")
+    return {"variant": list(va), "lane": list(la), "order": list(oa), "tuned": rc == 1}
+
+
+def autotune_save(path):
+    """Write the current device's tuned EM launch plans to a plan file (lines
+    of other devices in an existing file are kept)."""
+    check(_lib.load().gm_autotune_save(os.fsencode(path)), "gm_autotune_save")
+
+
+def autotune_load(path):
+    """Install the plans of a plan file that were tuned on a device like the
+    current one (same architecture and CU count); returns how many."""
+    rc = _lib.load().gm_autotune_load(os.fsencode(path))
+    check(min(rc, 0), "gm_autotune_load")
+    return rc
+
+
 def profile_enable(on=True):
     _lib.load().gm_profile_enable(1 if on else 0)
 

@@ -1,10 +1,13 @@
 // gm_api.hip -- the C ABI of libgmcr: argument checks, workspace layout and
 // launch sequencing.  All arithmetic happens in the kernels.
+#include <stdio.h>
 #include <string.h>
 
 #include "gm_compress_impl.h"
 
 #include <algorithm>
+#include <string>
+#include <vector>
 #include <mutex>
 
 namespace gm {
@@ -736,11 +739,15 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     return rc;
 }
 
-int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant, const int32_t* lane)
+namespace {
+
+// A plan from launch-plan codes (as in the autotune report), checked: every
+// variant built and covering its bucket, lanes in range, the launch order
+// (nullable: the built-in order) a permutation of the buckets.
+int plan_from_codes(int D, int kt, bool fp64, const int32_t* variant, const int32_t* lane, const int32_t* order,
+                    EmPlan& p)
 {
-    if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || !variant) return GM_EINVAL;
-    const int kt = kmax <= 8 ? 8 : 16;
-    EmPlan p = default_plan(D, kt, fp64 != 0);
+    p = default_plan(D, kt, fp64);
     for (int b = 0; b < gm::kNumBuckets; ++b) {
         const int code = variant[b];
         const int P = code / 1000, W = (code / 10) % 100, mode = code % 10;
@@ -761,11 +768,172 @@ int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const i
             p.lane[b] = (int8_t)lane[b];
         }
     }
+    if (order) {
+        bool seen[gm::kNumBuckets] = {};
+        for (int b = 0; b < gm::kNumBuckets; ++b) {
+            if (order[b] < 0 || order[b] >= gm::kNumBuckets || seen[order[b]]) return GM_EINVAL;
+            seen[order[b]] = true;
+            p.order[b] = (int8_t)order[b];
+        }
+    }
     p.tuned = true;
+    return GM_OK;
+}
+
+// ---- launch-plan file ----
+// One line per tuned plan:
+//   gmcr-plan 1 <arch> <CUs> <D> <kmax class> <fp64> <warm> v[12] lane[12] order[12]
+// The device key is the architecture name and CU count of the device the
+// plan was tuned on; a file may hold the plans of several devices.
+constexpr const char* kPlanTag = "gmcr-plan";
+constexpr int kPlanFileVersion = 1;
+
+bool device_key(char* arch, size_t n, int& cus)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    size_t i = 0;
+    for (; i + 1 < n && prop.gcnArchName[i] && prop.gcnArchName[i] != ' '; ++i) arch[i] = prop.gcnArchName[i];
+    arch[i] = 0;
+    cus = prop.multiProcessorCount;
+    return i > 0;
+}
+
+struct PlanLine {
+    char arch[64];
+    int cus, D, kt, fp64, warm;
+    int32_t v[gm::kNumBuckets], lane[gm::kNumBuckets], order[gm::kNumBuckets];
+};
+
+// parse one line; false if it is not a well-formed plan line
+bool parse_plan_line(const char* line, PlanLine& pl)
+{
+    char tag[16];
+    int ver = 0, used = 0;
+    if (sscanf(line, "%15s %d %63s %d %d %d %d %d%n", tag, &ver, pl.arch, &pl.cus, &pl.D, &pl.kt, &pl.fp64, &pl.warm,
+               &used) != 8)
+        return false;
+    if (strcmp(tag, kPlanTag) != 0 || ver != kPlanFileVersion) return false;
+    const char* q = line + used;
+    int32_t* dst[3] = {pl.v, pl.lane, pl.order};
+    for (int f = 0; f < 3; ++f)
+        for (int b = 0; b < gm::kNumBuckets; ++b) {
+            int x = 0, k = 0;
+            if (sscanf(q, "%d%n", &x, &k) != 1) return false;
+            dst[f][b] = x;
+            q += k;
+        }
+    while (*q == ' ' || *q == '\t' || *q == '\r' || *q == '\n') ++q;
+    return *q == 0 && (pl.D == 1 || pl.D == 3) && (pl.kt == 8 || pl.kt == 16) && (pl.fp64 == 0 || pl.fp64 == 1) &&
+           (pl.warm == 0 || pl.warm == 1);
+}
+
+}  // namespace
+
+int gm_autotune_set(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, const int32_t* variant, const int32_t* lane)
+{
+    if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || !variant) return GM_EINVAL;
+    const int kt = kmax <= 8 ? 8 : 16;
+    EmPlan p;
+    const int rc = plan_from_codes(D, kt, fp64 != 0, variant, lane, nullptr, p);
+    if (rc != GM_OK) return rc;
     EmPlan* slot = plan_slot(D, kt, fp64 != 0, warm != 0, true);
     if (!slot) return GM_EHIP;
     *slot = p;
     return GM_OK;
+}
+
+int gm_autotune_get(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, int32_t* variant, int32_t* lane,
+                    int32_t* order)
+{
+    if ((D != 1 && D != 3) || kmax < 1 || kmax > 16 || !variant) return GM_EINVAL;
+    const int kt = kmax <= 8 ? 8 : 16;
+    const EmPlan* slot = plan_slot(D, kt, fp64 != 0, warm != 0, false);
+    const EmPlan p = slot ? *slot : default_plan(D, kt, fp64 != 0);
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        variant[b] = gm::em_variant_code(p.per_thread[b], p.waves[b], p.mode[b]);
+        if (lane) lane[b] = p.lane[b];
+        if (order) order[b] = p.order[b];
+    }
+    return p.tuned ? 1 : 0;
+}
+
+int gm_autotune_save(const char* path)
+{
+    if (!path || !path[0]) return GM_EINVAL;
+    char arch[64];
+    int cus = 0, dev = 0;
+    if (!device_key(arch, sizeof(arch), cus) || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return GM_EHIP;
+    // keep the lines of other devices from an existing file
+    std::vector<std::string> keep;
+    if (FILE* f = fopen(path, "r")) {
+        char buf[1024];
+        while (fgets(buf, sizeof(buf), f)) {
+            PlanLine pl;
+            if (parse_plan_line(buf, pl) && !(strcmp(pl.arch, arch) == 0 && pl.cus == cus)) keep.emplace_back(buf);
+        }
+        fclose(f);
+    }
+    FILE* f = fopen(path, "w");
+    if (!f) return GM_EIO;
+    bool ok = true;
+    for (const std::string& l : keep) ok &= fputs(l.c_str(), f) >= 0;
+    for (int d3 = 0; d3 < 2; ++d3)
+        for (int k16 = 0; k16 < 2; ++k16)
+            for (int f64 = 0; f64 < 2; ++f64)
+                for (int w = 0; w < 2; ++w) {
+                    const EmPlan* p = g_plans[dev][d3][k16][f64][w];
+                    if (!p || !p->tuned) continue;
+                    ok &= fprintf(f, "%s %d %s %d %d %d %d %d", kPlanTag, kPlanFileVersion, arch, cus, d3 ? 3 : 1,
+                                  k16 ? 16 : 8, f64, w) > 0;
+                    for (int b = 0; b < gm::kNumBuckets; ++b)
+                        ok &= fprintf(f, " %d", gm::em_variant_code(p->per_thread[b], p->waves[b], p->mode[b])) > 0;
+                    for (int b = 0; b < gm::kNumBuckets; ++b) ok &= fprintf(f, " %d", p->lane[b]) > 0;
+                    for (int b = 0; b < gm::kNumBuckets; ++b) ok &= fprintf(f, " %d", p->order[b]) > 0;
+                    ok &= fputc('\n', f) != EOF;
+                }
+    ok &= fclose(f) == 0;
+    return ok ? GM_OK : GM_EIO;
+}
+
+int gm_autotune_load(const char* path)
+{
+    if (!path || !path[0]) return GM_EINVAL;
+    char arch[64];
+    int cus = 0;
+    if (!device_key(arch, sizeof(arch), cus)) return GM_EHIP;
+    FILE* f = fopen(path, "r");
+    if (!f) return GM_EIO;
+    // check every line first, install only a wholly valid file
+    std::vector<std::pair<PlanLine, EmPlan>> plans;
+    char buf[1024];
+    int rc = GM_OK;
+    while (rc == GM_OK && fgets(buf, sizeof(buf), f)) {
+        const char* q = buf;
+        while (*q == ' ' || *q == '\t') ++q;
+        if (*q == '\n' || *q == '\r' || *q == 0 || *q == '#') continue;
+        PlanLine pl;
+        if (!parse_plan_line(buf, pl)) {
+            rc = GM_EINVAL;
+            break;
+        }
+        if (strcmp(pl.arch, arch) != 0 || pl.cus != cus) continue;  // another device's plan
+        EmPlan p;
+        rc = plan_from_codes(pl.D, pl.kt, pl.fp64 != 0, pl.v, pl.lane, pl.order, p);
+        if (rc == GM_OK) plans.emplace_back(pl, p);
+    }
+    const bool read_err = ferror(f) != 0;
+    fclose(f);
+    if (read_err) return GM_EIO;
+    if (rc != GM_OK) return rc;
+    for (const auto& e : plans) {
+        EmPlan* slot = plan_slot(e.first.D, e.first.kt, e.first.fp64 != 0, e.first.warm != 0, true);
+        if (!slot) return GM_EHIP;
+        *slot = e.second;
+    }
+    return (int)plans.size();
 }
 
 int gm_autotune_reset(void)

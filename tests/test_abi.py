@@ -128,6 +128,39 @@ def test_launch_plan_codes_checked_on_host():
     assert setp(c) != -1
 
 
+def test_built_in_launch_plans_and_plan_file_arguments(tmp_path):
+    """gm_autotune_get reports the built-in plan where none is installed (here,
+    with no device visible, always): for 3V FP32 at kmax 16 the four-wave 5-,
+    6- and 7-particle builds for cells of 1025-1792 particles, eight waves of
+    5 and 8 register-resident particles for 2049-2560 and 2561-4096, the
+    16-wave lean build above; FP64 recomputes above 2048.  The plan-file
+    calls reject missing paths before they look for a device."""
+    from paper_2007_12273_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+
+    def get(D, kmax, fp64=0, warm=0):
+        v, ln, o = (ctypes.c_int32 * 12)(), (ctypes.c_int32 * 12)(), (ctypes.c_int32 * 12)()
+        rc = lib.gm_autotune_get(D, kmax, fp64, warm, v, ln, o)
+        return rc, list(v), list(ln), list(o)
+
+    rc, v, ln, o = get(3, 16)
+    if rc == 1:
+        pytest.skip("a device with a tuned plan is visible")
+    assert rc == 0
+    assert v == [2011, 4011, 4021, 4031, 4041, 5041, 6041, 7041, 4081, 5081, 8081, 8162], v
+    assert ln == list(range(12)) and o == list(range(11, -1, -1))
+    assert get(3, 16, warm=1)[1] == v
+    assert get(3, 16, fp64=1)[1] == [2011, 4011, 4021, 4031, 4041, 4051, 4061, 4071, 4081, 8050, 8080, 16080]
+    assert get(1, 16)[1][9:] == [4102, 4162, 8162]       # 1V: lean builds above 2048
+    assert get(3, 8)[1] == [1011, 2011, 4011, 8011, 8021, 8031, 8041, 8051, 8061, 8071, 8081, 16080]
+    assert lib.gm_autotune_get(2, 16, 0, 0, (ctypes.c_int32 * 12)(), None, None) == -1
+    assert lib.gm_autotune_get(3, 16, 0, 0, None, None, None) == -1
+    assert lib.gm_autotune_save(None) == -1 and lib.gm_autotune_save(b"") == -1
+    assert lib.gm_autotune_load(None) == -1 and lib.gm_autotune_load(b"") == -1
+
+
 def test_warm_model_files_checked_before_any_device_work(tmp_path):
     """gm_warm_load reads and checks the whole file before it allocates:
     missing or truncated files are GM_EIO, foreign ones GM_EINVAL."""

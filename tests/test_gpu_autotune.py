@@ -98,3 +98,56 @@ def test_autotune_installs_a_working_plan():
         fp32_parity.check(g, o, sub, res, "tuned plan replay")
     finally:
         api.autotune_reset()
+
+
+def test_plan_file_round_trip(tmp_path):
+    """A plan written by gm_autotune_save and read back by gm_autotune_load
+    after a reset is the same plan (variants, streams, launch order) and
+    gives bit-identical compress results; lines of another device are
+    skipped and kept by a later save; a file with an invalid line installs
+    nothing."""
+    from paper_2007_12273_amd import api
+    d = synth.make("weibel_3v")
+    off = d["cell_off"]
+    nc = 256
+    sub = dict(v=d["v"][:off[nc]], alpha=d["alpha"][:off[nc]], cell_off=off[:nc + 1], D=3)
+    v, a, offg = to_gpu(sub)
+    comp = api.Compressor(nc, 3, 16, device=dev(), seed=2003)
+    path = tmp_path / "plans.txt"
+    codes = [2011, 4011, 4021, 4031, 8021, 5041, 6041, 7041, 4081, 5081, 8081, 8162]
+    lanes = [11 - b for b in range(12)]
+    order = [5, 4, 3, 2, 1, 0, 11, 10, 9, 8, 7, 6]
+    try:
+        api.autotune_reset()
+        assert not api.autotune_get(3, 16)["tuned"]
+        api.autotune_set(3, 16, codes, lanes)
+        ref = host(comp(v, a, offg).as_dict())
+        other = "gmcr-plan 1 gfx000 7 3 16 0 0 " + " ".join(["16080"] * 12 + ["0"] * 12 + [str(b) for b in range(12)])
+        path.write_text("# plans\n" + other + "\n")
+        api.autotune_save(path)
+        lines = path.read_text().splitlines()
+        assert other in lines and len(lines) == 2, lines
+        mine = [l for l in lines if l != other][0].split()
+        assert [int(x) for x in mine[8:20]] == codes and [int(x) for x in mine[20:32]] == lanes, mine
+        mine[32:44] = [str(x) for x in order]
+        text = "\n".join([other, " ".join(mine)]) + "\n"
+        path.write_text(text)
+        api.autotune_reset()
+        assert not api.autotune_get(3, 16)["tuned"]
+        assert api.autotune_load(path) == 1
+        loaded = api.autotune_get(3, 16)
+        assert loaded == {"variant": codes, "lane": lanes, "order": order, "tuned": True}, loaded
+        again = host(comp(v, a, offg).as_dict())
+        for k in ("K", "sweeps", "visits", "status", "L_pen", "omega", "mu", "sigma"):
+            assert np.array_equal(again[k], ref[k]), k
+        # an invalid line (a variant that does not cover its bucket, an order
+        # that is not a permutation) rejects the whole file
+        for bad in (" ".join(mine[:19] + ["4081"] + mine[20:]), " ".join(mine[:43] + ["5"])):
+            api.autotune_reset()
+            bad_path = tmp_path / "bad.txt"
+            bad_path.write_text(other + "\n" + bad + "\n")
+            with pytest.raises(RuntimeError):
+                api.autotune_load(bad_path)
+            assert not api.autotune_get(3, 16)["tuned"]
+    finally:
+        api.autotune_reset()
