@@ -404,7 +404,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2007_12273_amd import api, synth
+    from paper_2007_12273_amd import _lib, api, synth
     from paper_2007_12273_amd import warm as warmlib
 
     data = synth.make(args.workload)
@@ -541,6 +541,8 @@ def main():
         # output after the judged fallback: cold fit in the judged cells
         Kout = wr["K"].copy()
         Kout[judged] = cold["K"][judged]
+        Sout = wr["status"].copy()
+        Sout[judged] = cold["status"][judged]
         q = lambda x: [float(np.quantile(x, t)) for t in (0.01, 0.1, 0.5, 0.9, 0.99)]
         line_extra = {
             "plain_em": {"value": n_part / (ms_cold * 1e-3), "ms_per_step": ms_cold, "phase_ms": ph_cold,
@@ -576,6 +578,7 @@ def main():
         phases = ph_warm
     else:
         ms, em_ms, visits, phases, Kout, wr = ms_cold, ph_cold["em"], cold["visits"], ph_cold, cold["K"], cold
+        Sout = cold["status"]
 
     if args.visits_out:
         np.savez(args.visits_out, n=counts, visits_cold=cold["visits"], visits_warm=wr["visits"])
@@ -625,6 +628,9 @@ def main():
         "mean_sweeps": float(wr["sweeps"].mean()),
         # the paper's ratio: particles per Gaussian component
         "compression_ratio": float(counts.sum() / max(1, Kout.sum())),
+        # cells per output K (0 .. kmax) and per status flag of the output record
+        "K_histogram": np.bincount(Kout, minlength=kmax + 1).tolist(),
+        "status_counts": {name: int(((Sout & bit) != 0).sum()) for name, bit in _lib.STATUS.items()},
         "conservation": cons,
     }
     line.update(line_extra)

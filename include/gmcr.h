@@ -246,9 +246,10 @@ int gm_autotune_reset(void);
 /* The plan gm_compress uses on the current device for (D, kmax class,
  * fp64, warm): variant[b] coded as in the report, and (nullable) lane[b]
  * and order[b] (launch order, 0 first) for the twelve buckets, caller-owned
- * arrays of 12.  Returns 1 for a tuned, hand-set or loaded plan, 0 for the
- * built-in one (also when no device is visible), GM_EINVAL for bad
- * arguments. */
+ * arrays of 12.  Returns 1 for a plan installed by gm_autotune (also where
+ * it kept the built-in plan), gm_autotune_set or gm_autotune_load, 0 where
+ * none is installed (the built-in plan; also when no device is visible),
+ * GM_EINVAL for bad arguments. */
 int gm_autotune_get(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, int32_t* variant, int32_t* lane,
                     int32_t* order);
 
@@ -257,8 +258,8 @@ int gm_autotune_get(int32_t D, int32_t kmax, int32_t fp64, int32_t warm, int32_t
  *   variant[12] lane[12] order[12]),
  * keyed by the device (architecture name and CU count), D, kmax class,
  * precision and kind of start, with the variant, stream and launch order of
- * every length bucket.  gm_autotune_save writes the current device's tuned
- * plans to `path`, keeping the lines of other devices already in the file;
+ * every length bucket.  gm_autotune_save writes the current device's
+ * installed plans (those gm_autotune_get reports as 1) to `path`, keeping the lines of other devices already in the file;
  * GM_EINVAL (NULL or empty path), GM_EHIP (no device), GM_EIO.
  * gm_autotune_load reads `path` and installs the plans whose device key is
  * the current device's, each checked as by gm_autotune_set (and the order a

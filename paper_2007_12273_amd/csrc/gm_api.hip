@@ -717,8 +717,14 @@ int gm_autotune(const double* v, const double* alpha, const int64_t* cell_off, i
     const EmPlan& chosen = cands[rc == GM_OK ? pick : 0];
     if (rc == GM_OK) {
         EmPlan* slot = plan_slot(D, kt, fp64, warm, true);
-        if (!slot) rc = GM_EHIP;
-        else *slot = chosen;
+        if (!slot) {
+            rc = GM_EHIP;
+        } else {
+            // installed as a measured choice also where it is the built-in
+            // plan, so that a plan file keeps the decision
+            *slot = chosen;
+            slot->tuned = true;
+        }
     }
     // leave a complete compress result in `out`
     if (rc == GM_OK && (requeue() || launch_em_phase(D, fp64, kt, chosen, a, n_cells, st) ||

@@ -87,6 +87,9 @@ def test_autotune_installs_a_working_plan():
         # build of 8 recomputed particles
         assert rep["variant"][9] in (5081, 4102), rep["variant"]
         assert rep["variant"][10] in (8081, 4162) and rep["variant"][11] == 8162, rep["variant"]
+        # the installed plan (tuned or the kept built-in one) is the reported one
+        inst = api.autotune_get(3, 16)
+        assert inst["tuned"] and inst["variant"] == list(rep["variant"]) and inst["lane"] == list(rep["lane"]), inst
         tuned = host(comp.out.as_dict())
         again = host(comp(v, a, offg).as_dict())
         for k in ("K", "sweeps", "status"):
