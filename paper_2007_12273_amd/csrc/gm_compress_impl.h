@@ -1724,14 +1724,45 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(CompressArgs A)
         L_pen = A.out.L_pen[c];
         sweeps = A.out.sweeps[c];
         visits = A.out.visits[c];
+        if (tid == 0) s_ok = 0;  // bit 0: a floor was needed, bit 1: a component did not factor
+        sync();
         if (tid < K) {
             const size_t sk = (size_t)c * kmax + tid;
             double mu[D], S[NT];
             for (int d = 0; d < D; ++d) mu[d] = A.out.mu[sk * D + d];
             for (int q = 0; q < NT; ++q) S[q] = A.out.sigma[sk * NT + q];
-            make_f64<D>(cf[tid], mu, S, A.out.omega[sk]);
+            if (!make_f64<D>(cf[tid], mu, S, A.out.omega[sk])) {
+                // a covariance that factored in FP32 iterations (floored or
+                // not) can fail the FP64 factorisation when it is nearly
+                // singular: the iteration's floor, eps I with eps = 1e-12
+                // tr(C)/D growing tenfold; if even that fails the cell takes
+                // the closed form below, so no component is left unset
+                double eps = 1e-12 * ci->trC / D;
+                bool ok = false;
+                for (int it = 0; it < 40 && !ok; ++it) {
+                    for (int i = 0; i < D; ++i) S[tri_idx<D>(i, i)] += eps;
+                    ok = make_f64<D>(cf[tid], mu, S, A.out.omega[sk]);
+                    eps *= 10.0;
+                }
+                atomicOr(&s_ok, ok ? 1 : 2);
+            }
         }
         sync();
+        const int fac = s_ok;
+        if (fac & 2) {
+            // no FP64 factor for some component: the closed form
+            K = 1;
+            status |= GM_ST_DEGENERATE;
+            if (tid == 0) {
+                outw[0] = 1.0;
+                for (int d = 0; d < D; ++d) outmu[0][d] = 0.0;
+                for (int q = 0; q < NT; ++q) outS[0][q] = ci->C[q];
+                make_f64<D>(cf[0], outmu[0], outS[0], 1.0);
+            }
+            sync();
+        } else if (fac & 1) {
+            status |= GM_ST_COV_FLOOR;
+        }
         // gamma_pk = a_p exp(l_k - mx_p) / sum_j exp(l_j - mx_p): a ratio of
         // the same exponentials, so sum_k gamma_pk = a_p to rounding (the
         // cache keeps 1 / sum)
