@@ -75,9 +75,10 @@ typedef struct gm_opts {
     int32_t max_sweeps;   /* cap on EM sweeps (default 1000) */
     double tol_rel;       /* stop when |L_s - L_{s-1}| <= tol_rel |L_s| after a sweep
                              without annihilation (default 1e-7); FP32
-                             iterations also stop after such a sweep whose
-                             L_s < L_{s-1}: the component updates do not
-                             lower L, so that change is FP32 rounding of L */
+                             iterations, which resolve L only to about 1e-7 n,
+                             also stop after such a sweep with |L_s - L_{s-1}|
+                             <= tol_rel n or L_s < L_{s-1} (the component
+                             updates do not lower L) */
     uint64_t seed;        /* seed of the cold-start particle choice */
     int32_t estep_fp64;   /* 0: EM iterations in FP32 (default); 1: in FP64 */
     int32_t outer_k;      /* 0: one run of the sweeps (the paper's algorithm, default);

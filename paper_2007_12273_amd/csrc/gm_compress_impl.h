@@ -1133,13 +1133,13 @@ void k_em(CompressArgs A_in)
                     }
                     if (!isfinite(L_s)) break;  // the objective is undefined: no further sweep can help
                     if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= tol * fabs(L_s)) break;
-                    // FP32: the iteration does not lower L between sweeps without an
-                    // annihilation, so a lower L is FP32 rounding of the
-                    // per-particle log-densities that L sums (about 1e-7 of N):
-                    // the change of L is below what FP32 resolves, and the fit
+                    // FP32 resolves L only to the rounding of the per-particle
+                    // log-densities it sums, about 1e-7 of N: a change of L within
+                    // tol N, or a lower L (the iteration does not lower L between
+                    // sweeps without an annihilation), is below that, and the fit
                     // stops as converged
                     if constexpr (std::is_same<R, float>::value)
-                        if (s >= 2 && !annihilated && L_s < L_prev) break;
+                        if (s >= 2 && !annihilated && (L_s < L_prev || fabs(L_s - L_prev) <= tol * N)) break;
                     if (s == max_sweeps) {
                         status |= GM_ST_MAXSWEEPS;
                         break;
@@ -1470,7 +1470,7 @@ __global__ __launch_bounds__(kBigThreads) void k_em_big(CompressArgs A)
                     if (!isfinite(L_s)) break;
                     if (s >= 2 && !annihilated && fabs(L_s - L_prev) <= A.tol * fabs(L_s)) break;
                     if constexpr (std::is_same<R, float>::value)
-                        if (s >= 2 && !annihilated && L_s < L_prev) break;  // as in k_em
+                        if (s >= 2 && !annihilated && (L_s < L_prev || fabs(L_s - L_prev) <= A.tol * N)) break;  // as in k_em
                     if (s == A.max_sweeps) {
                         status |= GM_ST_MAXSWEEPS;
                         break;

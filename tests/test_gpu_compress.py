@@ -226,3 +226,35 @@ def test_deterministic_across_runs():
     g2 = _gpu_compress(d, 16, seed=5, max_sweeps=60)
     for k in g1:
         assert np.array_equal(g1[k], g2[k]), k
+
+
+def test_fp32_fits_stop_at_their_resolution_where_L_is_small():
+    """FP32 iterations stop at their resolution of L, about 1e-7 N: a change
+    within tol N, or a drop of L (the component updates do not lower it).
+    The cells here are rescaled so that their fitted L is N/100 (scaling v
+    by s shifts L by -N D ln s): the relative test |dL| <= 1e-7 |L| then asks
+    for changes far below FP32 rounding of L, and without the rule such fits
+    run to the sweep cap.  Each FP32 fit must stop where the FP64 oracle's does not run
+    to the cap either, within a few times its sweeps, and meet the FP32
+    bars against the oracle replayed to its stop."""
+    D, kmax, seed = 3, 8, 23
+    d = synth.random_cells(41, 24, D, 300, 1500, k_lo=2, k_hi=3)
+    off = d["cell_off"]
+    n = np.diff(off)
+    o0 = oracle.compress(d["v"], d["alpha"], off, kmax=kmax, seed=seed, max_sweeps=1000)
+    v = d["v"].copy()
+    for c in range(len(n)):
+        s = np.exp((o0["L_pen"][c] - n[c] / 100.0) / (n[c] * D))
+        v[off[c]:off[c + 1]] *= s
+    ds = dict(v=v, alpha=d["alpha"], cell_off=off)
+    o = oracle.compress(v, d["alpha"], off, kmax=kmax, seed=seed, max_sweeps=1000)
+    print("rescaled L / N: median %.3f" % np.median(o["L_pen"] / n))
+    assert np.all(np.abs(o["L_pen"]) < 0.1 * n)
+    g = _gpu_compress(ds, kmax, seed=seed, max_sweeps=1000)
+    cap = oracle.STATUS["MAXSWEEPS"]
+    free = (o["status"] & cap) == 0
+    print("sweeps, oracle / GPU FP32:", list(zip(o["sweeps"].tolist(), g["sweeps"].tolist())))
+    assert free.sum() >= len(n) // 2
+    assert np.all((g["status"][free] & cap) == 0)
+    assert np.all(g["sweeps"][free] <= 3 * o["sweeps"][free] + 20)
+    fp32_parity.converged(g, ds, kmax, seed, "rescaled small-L cells")
