@@ -187,7 +187,12 @@ int gm_compress_noalloc(const double* v, const double* alpha, const int64_t* cel
  * 2560, 4096, 8192 at kmax > 8), each a
  * persistent launch whose workgroups take cells from a queue, each on a
  * library stream of its own (cells of more than 8192 particles run on the
- * caller's stream), so that all thirteen launches run concurrently.  HIP
+ * caller's stream), so that all thirteen launches run concurrently.  The
+ * launches of buckets whose workgroups fill a compute unit's register file
+ * (eight or more waves of a standard build, sixteen of a lean one) are
+ * released first and the others about 40 us later, after a one-wave wait
+ * kernel on the caller's stream that ends at once when those buckets hold
+ * no cell.  HIP
  * maps streams onto GPU_MAX_HW_QUEUES hardware queues per process (default
  * 4): run with GPU_MAX_HW_QUEUES >= 13 (set before the HIP runtime starts)
  * for them to overlap; with fewer, launches sharing a queue run one after

@@ -72,10 +72,34 @@ constexpr int kLanes = gm::kNumBuckets + 1;
 struct Fork {
     hipStream_t aux[kLanes - 1];
     hipEvent_t fork;
+    hipEvent_t fork2;  // releases the launches that do not fill a CU
     hipEvent_t join[kLanes - 1];
+    long long hold_ticks;  // kHoldUs in ticks of the device's wall clock
 };
 constexpr int kMaxDevices = 64;
 Fork* g_fork[kMaxDevices] = {};
+
+// The EM phase releases its launches in two steps.  A bucket whose
+// workgroups fill a CU's register file (eight or more waves of a standard
+// build, sixteen of a lean one) can only start on an empty CU; launched
+// together with the smaller buckets, whose persistent workgroups spread
+// over every CU first, such a bucket's cells (in 3V the slowest fits)
+// started up to several milliseconds late.  Its launches are therefore
+// released first, and the others kHoldUs later, after a one-wave wait on
+// the caller's stream that ends at once when those buckets hold no cell.
+constexpr int kHoldUs = 40;
+__global__ void k_hold(long long ticks, const int32_t* plan, unsigned heavy)
+{
+    int cells = 0;
+    for (int b = 0; b < gm::kNumBuckets; ++b)
+        if ((heavy >> b) & 1u) cells += plan[gm::PLAN_COUNT + b];
+    if (cells == 0) return;
+    const long long t0 = wall_clock64();
+    for (int i = 0; i < (1 << 16); ++i) {  // bounded: about 13 ms of sleeps at most
+        if (wall_clock64() - t0 >= ticks) break;
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
 
 Fork* fork_for_device()
 {
@@ -88,6 +112,10 @@ Fork* fork_for_device()
         if (hipEventCreateWithFlags(&f->join[i], hipEventDisableTiming) != hipSuccess) return nullptr;
     }
     if (hipEventCreateWithFlags(&f->fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f->fork2, hipEventDisableTiming) != hipSuccess) return nullptr;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) return nullptr;
+    f->hold_ticks = (long long)khz * kHoldUs / 1000;
     g_fork[dev] = f;
     return f;
 }
@@ -234,9 +262,36 @@ int launch_em_phase(int D, bool fp64, int kt, const EmPlan& p, gm::CompressArgs&
     if (hipEventRecord(fk->fork, st) != hipSuccess) return -1;
     for (int i = 0; i < kLanes - 1; ++i)
         if (hipStreamWaitEvent(fk->aux[i], fk->fork, 0) != hipSuccess) return -1;
+    // buckets whose workgroups fill a CU first, then, after the hold, the rest
+    bool heavy[gm::kNumBuckets];
+    bool any_heavy = false, any_light = false;
+    unsigned heavy_mask = 0;
+    for (int b = 0; b < gm::kNumBuckets; ++b) {
+        const int fill = (p.mode[b] & gm::kModeLean) ? 16 : 8;
+        heavy[b] = p.waves[b] >= fill && p.lane[b] != kLanes - 1;  // none waits behind the hold
+        any_heavy |= heavy[b];
+        any_light |= !heavy[b];
+        if (heavy[b]) heavy_mask |= 1u << b;
+    }
     for (int i = 0; i < gm::kNumBuckets; ++i) {
         const int b = p.order[i];
-        if (launch_em_bucket(D, fp64, kt, b, p, a, n_cells, lanes[p.lane[b]])) return -1;
+        if (heavy[b] && launch_em_bucket(D, fp64, kt, b, p, a, n_cells, lanes[p.lane[b]])) return -1;
+    }
+    if (any_heavy && any_light) {
+        k_hold<<<1, 64, 0, st>>>(fk->hold_ticks, a.plan, heavy_mask);
+        if (hipGetLastError() != hipSuccess) return -1;
+        if (hipEventRecord(fk->fork2, st) != hipSuccess) return -1;
+        bool waited[kLanes] = {};
+        for (int b = 0; b < gm::kNumBuckets; ++b) {
+            const int l = p.lane[b];
+            if (heavy[b] || l == kLanes - 1 || waited[l]) continue;
+            if (hipStreamWaitEvent(lanes[l], fk->fork2, 0) != hipSuccess) return -1;
+            waited[l] = true;
+        }
+    }
+    for (int i = 0; i < gm::kNumBuckets; ++i) {
+        const int b = p.order[i];
+        if (!heavy[b] && launch_em_bucket(D, fp64, kt, b, p, a, n_cells, lanes[p.lane[b]])) return -1;
     }
     // cells larger than the buckets hold, on the caller's stream
     {
