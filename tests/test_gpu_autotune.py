@@ -154,3 +154,43 @@ def test_plan_file_round_trip(tmp_path):
             assert not api.autotune_get(3, 16)["tuned"]
     finally:
         api.autotune_reset()
+
+
+@pytest.mark.parametrize("which", ["weibel", "no_large_cells"])
+def test_two_step_release_leaves_results_unchanged(which):
+    """The EM launches of the buckets whose workgroups fill a CU are released
+    before the others (with a short device-side wait between); a plan with
+    the same variants whose CU-filling buckets sit on the caller's stream
+    releases everything at once.  Each cell is fitted by the same variant
+    either way, so the two records are bit-identical: with the large-cell
+    buckets populated (Weibel-like cells of up to 5000 particles) and empty
+    (the wait then ends at once)."""
+    from paper_2007_12273_amd import api
+    d = synth.make("weibel_3v")
+    off = d["cell_off"]
+    n = np.diff(off)
+    if which == "weibel":
+        cells = np.arange(768)
+    else:
+        cells = np.flatnonzero(n <= 1792)[:768]
+    parts = [dict(v=d["v"][off[c]:off[c + 1]], alpha=d["alpha"][off[c]:off[c + 1]],
+                  cell_off=np.array([0, n[c]], dtype=np.int64), D=3) for c in cells]
+    sub = synth.concat_cells(parts)
+    sizes = np.diff(sub["cell_off"])
+    assert (sizes > 1792).any() == (which == "weibel")
+    v, a, offg = to_gpu(sub)
+    try:
+        api.autotune_reset()
+        plan = api.autotune_get(3, 16)
+        codes = plan["variant"]
+        # waves of each code; 8+ (16+ for lean builds) fill a CU
+        fills = [(c // 10) % 100 >= (16 if c % 10 & 2 else 8) for c in codes]
+        assert any(fills) and not all(fills), codes
+        staged = host(api.compress(v, a, offg, 16, seed=31))
+        api.autotune_set(3, 16, codes, [12 if f else b for b, f in enumerate(fills)])
+        together = host(api.compress(v, a, offg, 16, seed=31))
+        for k in staged:
+            assert np.array_equal(staged[k], together[k], equal_nan=True), k
+        assert (staged["K"] > 0).all()
+    finally:
+        api.autotune_reset()
